@@ -1,0 +1,217 @@
+"""Throughput benchmark of the PIC step on one MI355X.
+
+Workload (one GPU): 256^3 cells in 64 boxes of 64^3, a slab z in [115, 141)
+of electrons and protons (mass ratio 1836) at 8 particles per cell each
+(27,262,976 particles), quadratic shapes, FP32, dt = 0.5, periodic, seeded
+thermal electrons (u_th = 0.005) and protons at rest, per-box device-clock
+costs accumulated every step.
+
+A step is the whole hot path: gather, Boris push, Esirkepov deposit, Yee
+update, in-kernel per-box clock costs, and the periodic tile re-sort.
+`value` is particle-steps/s over the timed steps, inputs resident in HBM.
+The roofline entry is the gather-push-deposit kernel's algorithmic HBM bytes
+per launch over its average launch time (HIP events on the library's stream
+inside the timed region).  `cpu_baseline` times the FP64 oracle on the host
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+P = 4  # bytes per float (FP32 workload)
+
+
+def workload():
+    import picsynth
+    return picsynth.config("c2")
+
+
+def make_ctx(wl, stream=None):
+    from paper_2104_11385_amd import picbal as pb
+    sp = []
+    for s in wl.species:
+        sp.append(pb.Species(s.charge, s.mass, s.density, load_mode=1, ppc=s.ppc, region_lo=s.region_lo,
+                             region_hi=s.region_hi, u_th=s.u_th, u_drift=s.u_drift))
+    return pb.pic_init(wl.n, wl.boxes, sp, wl.dt, wl.order, pb.PIC_FP32, wl.seed, b_ext=wl.b_ext, stream=stream)
+
+
+def algorithmic_bytes(wl):
+    """Per step: particles 13P (read x,u,w; write x,u), all cells 15P (Yee:
+    read E,B,J; write E,B), occupied cells 9P (gather E,B; deposit J)."""
+    import picsynth
+    n_p = sum(picsynth.species_count(wl, s) for s in range(len(wl.species)))
+    cells = int(np.prod(wl.n))
+    lo, hi = np.array(wl.species[0].region_lo), np.array(wl.species[0].region_hi)
+    occ = int(np.prod(hi - lo))
+    gpd = n_p * 13 * P + occ * 9 * P
+    step = gpd + cells * 15 * P
+    return n_p, gpd, step
+
+
+def run_gpu(args):
+    import torch
+    from paper_2104_11385_amd import picbal as pb
+
+    wl = workload()
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = make_ctx(wl, stream=stream)
+    n_p, gpd_bytes, step_bytes = algorithmic_bytes(wl)
+    mode = {"per_box": pb.PIC_LAUNCH_PER_BOX, "batched": pb.PIC_LAUNCH_BATCHED,
+            "persistent": pb.PIC_LAUNCH_PERSISTENT}[args.mode]
+    if args.tune:
+        ctx.set_launch_mode(mode, False)
+        t, ms = ctx.autotune(3)
+        print(f"[bench] autotuned {t.as_dict()} {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    tun = ctx.get_tuning()
+    if args.sort_interval:
+        ctx.set_tuning(sort_interval=args.sort_interval)
+        tun = ctx.get_tuning()
+
+    def timed(mode_, graph, steps, warm, kernel_events):
+        ctx.set_launch_mode(mode_, graph)
+        ctx.step(warm)
+        ctx.sync()
+        ctx.kernel_timing(kernel_events)
+        ms0, n0 = ctx.kernel_times()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms1, n1 = ctx.kernel_times()
+        ctx.kernel_timing(False)
+        return (t1 - t0) * 1e3 / steps, ms1 - ms0, n1 - n0
+
+    results = {}
+    # main timed region: selected mode, kernel events on the library's stream
+    ms_step, kms, kn = timed(mode, False, args.steps, args.warmup, True)
+    results["main"] = ms_step
+    gpd_ms = kms[0] / max(1, kn[0])
+    # same mode replayed from a captured graph (no per-kernel events possible)
+    ms_graph, _, _ = timed(mode, True, args.steps, 2, False)
+    extra = {}
+    if not args.quick:
+        for name, m in (("per_box", pb.PIC_LAUNCH_PER_BOX), ("batched", pb.PIC_LAUNCH_BATCHED),
+                        ("persistent", pb.PIC_LAUNCH_PERSISTENT)):
+            if m == mode:
+                extra[name] = ms_step
+                continue
+            extra[name], _, _ = timed(m, False, max(5, args.steps // 4), 2, False)
+        extra["persistent_graph"] = ms_graph if mode == pb.PIC_LAUNCH_PERSISTENT else None
+    best_ms = min(ms_step, ms_graph)
+    slow = ctx.slow_path_count()
+    costs, _ = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
+    counts = ctx.box_counts().sum(axis=1)
+    loaded = counts > 0
+    rho = None
+    if loaded.sum() > 2:
+        from scipy.stats import spearmanr
+        rho = float(spearmanr(costs[loaded], counts[loaded]).statistic)
+    ctx.finalize()
+    return {
+        "n_p": n_p, "ms_per_step": best_ms, "ms_eager_events": ms_step, "ms_graph": ms_graph,
+        "gpd_ms": gpd_ms, "gpd_launches_per_step": float(kn[0]) / args.steps,
+        "yee_ms": kms[1] / max(1, kn[1]), "sort_ms_total": kms[2], "gpd_bytes": gpd_bytes,
+        "step_bytes": step_bytes, "modes_ms": extra, "tuning": tun.as_dict(), "slow_path": slow,
+        "timer_cost_spearman_vs_count": rho,
+    }
+
+
+def cpu_baseline(sample_particles=3_000_000):
+    """The FP64 oracle on the host: one step of a particle sample of the same
+    workload (full grid, so the Yee update is included once), scaled to the
+    full particle count: rate = N_p / (N_p * t_particle + t_yee)."""
+    import oracle
+    import picsynth
+    wl = workload()
+    n = np.array(wl.n)
+    q = np.array([s.charge for s in wl.species]); m = np.array([s.mass for s in wl.species])
+    xs, us, ws, sps = [], [], [], []
+    per = sample_particles // len(wl.species)
+    for s in range(len(wl.species)):
+        tot = picsynth.species_count(wl, s)
+        idx = np.linspace(0, tot - 1, per).astype(np.int64)
+        x, u, w, _ = picsynth.particles(wl, s, idx)
+        xs.append(x); us.append(u); ws.append(w); sps.append(np.full(per, s, np.int32))
+    x = np.ascontiguousarray(np.concatenate(xs)); u = np.ascontiguousarray(np.concatenate(us))
+    w = np.concatenate(ws); sp = np.concatenate(sps)
+    F = np.zeros((9, n[2], n[1], n[0]))
+    F.fill(0.0)  # touch the pages before timing
+    t0 = time.perf_counter()
+    oracle.pic_step(wl.order, n, wl.dt, x, u, w, sp, q, m, F, 1)
+    t_step = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.yee(n, wl.dt, F)
+    t_yee = time.perf_counter() - t0
+    t_part = max(1e-12, (t_step - t_yee) / len(w))
+    n_p = sum(picsynth.species_count(wl, s) for s in range(len(wl.species)))
+    rate = n_p / (n_p * t_part + t_yee)
+    return {"value": rate, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 step of {len(w)} particles (evenly spaced ids of both species) on the full "
+                      f"256^3 grid, FP64, single thread; Yee {t_yee:.2f} s + particles {t_step - t_yee:.2f} s, "
+                      f"scaled to {n_p} particles"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--mode", default="persistent", choices=["per_box", "batched", "persistent"])
+    ap.add_argument("--sort-interval", type=int, default=0)
+    ap.add_argument("--tune", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the other launch modes")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    r = run_gpu(args)
+    ms = r["ms_per_step"]
+    value = r["n_p"] / (ms * 1e-3)
+    gpd_gbs = r["gpd_bytes"] / (r["gpd_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "particle-steps/s at 1 GPU (% HBM roofline)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Philox slab plasma, generated on the device)",
+        "config": {"workload": "256^3 cells, 64 boxes of 64^3, slab z in [115,141) of e- and p+ at 8 ppc each "
+                               "(27,262,976 particles), quadratic shapes, FP32, dt 0.5, periodic",
+                   "launch": args.mode, "tuning": r["tuning"]},
+        "roofline": {"bound": "hbm", "achieved": gpd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gpd_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "gather-push-deposit", "kernel_ms": r["gpd_ms"],
+                     "algorithmic_bytes_per_launch": r["gpd_bytes"]},
+        "step_hbm_frac": r["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "modes_ms_per_step": r["modes_ms"],
+        "ms_graph": r["ms_graph"], "ms_eager": r["ms_eager_events"],
+        "yee_ms": r["yee_ms"], "slow_path_particles": r["slow_path"],
+        "timer_cost_spearman_vs_count": r["timer_cost_spearman_vs_count"],
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

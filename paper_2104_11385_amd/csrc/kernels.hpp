@@ -1,0 +1,107 @@
+// Host-side launchers of the PIC kernels (implemented in pic_kernels.hip).
+#pragma once
+
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace pb {
+
+// Precision-erased particle arrays.
+struct ParticlesRaw {
+    uint32_t *cell = nullptr;
+    void *f[3] = {nullptr, nullptr, nullptr};
+    void *u[3] = {nullptr, nullptr, nullptr};
+    void *w = nullptr;
+    int64_t *id = nullptr;
+    uint8_t *sp = nullptr;
+};
+
+// On-device loader of one species (recipe: Philox4x32-10 words -> cell
+// offsets and Box-Muller normals; see the Python input generator).
+struct LoadArgs {
+    int mode;                 // 1: fixed ppc in a region, 2: per-box ppc
+    int rlo[3], rext[3];
+    int ppc;
+    const int64_t *box_base;  // [nb+1] prefix of cells*ppc (mode 2)
+    const int32_t *box_ppc;   // [nb]
+    const int *boxes6;        // [nb][6]
+    int nb;
+    int64_t n;                // particles of this species
+    int64_t out_base;         // first slot in the particle arrays
+    int species;
+    uint32_t k0, k1;          // Philox key
+    double uth[3], udrift[3];
+    double density;
+};
+
+struct SortScratch {
+    int nseg;                 // ntiles * nsp
+    uint32_t *cellcnt;        // [nseg * Tvol]
+    uint32_t *cellstart;      // [nseg * Tvol]
+    int *segtot;              // [nseg]
+    int *segstart;            // [nseg + 1]
+    uint32_t *key, *rank;     // [capacity]
+    uint32_t *table;          // [capacity]
+};
+
+struct QueueScratch {
+    int ncls;
+    int *cls_cnt;             // [ncls]
+    int *cursor;              // [ncls]
+    int *queue_len;           // [1]
+    int *queue_head;          // [1]
+    int4 *queue;              // [max items]
+};
+
+struct FeatScratch {
+    uint32_t *cellcount;      // [n cells]
+    unsigned long long *spcnt;    // [nb][2]
+    unsigned long long *edge;     // [nb]
+    double *usum;                 // [nb]
+};
+
+struct GpdLaunch {
+    ParticlesRaw P;
+    const int *segstart;
+    const TileDesc *tiles;
+    const void *EB[6];
+    void *J[3];
+    int n[3];
+    int nsp;
+    double dt;
+    double bext[3];
+    double h[kMaxSpecies];
+    double coefq[kMaxSpecies];
+    unsigned long long *cycles, *rtc;
+    unsigned int *slow;
+    int mode;
+    int tile_base;
+    int species_only;
+    const int4 *queue;
+    const int *queue_len;
+    int *queue_head;
+    int tile[3];
+    int halo;
+    unsigned grid, block;
+};
+
+hipError_t launch_load(int prec, const ParticlesRaw &P, const LoadArgs &a, hipStream_t st);
+hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, int np, const Geom &G,
+                       const SortScratch &W, hipStream_t st);
+hipError_t launch_queue(const int *segstart, int ntiles, int nsp, int chunk, const QueueScratch &Q, hipStream_t st);
+hipError_t launch_set_int(int *p, int v, hipStream_t st);
+hipError_t launch_fill_f(int prec, void *a, double v, size_t n, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *a, size_t n, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st);
+hipError_t launch_fill_f64(double *a, size_t n, hipStream_t st);
+hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st);
+bool gpd_supported(const int tile[3], int halo);
+size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo);
+hipError_t launch_yee(int prec, void *const F[9], void *const Jnext[3], const int n[3], double dt, hipStream_t st);
+hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,
+                             hipStream_t st);
+hipError_t launch_features(int prec, const ParticlesRaw &P, int np, const Geom &G, int nb, const int *box_hi,
+                           const FeatScratch &S, float *feat, hipStream_t st);
+
+}  // namespace pb

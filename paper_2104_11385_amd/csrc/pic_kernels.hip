@@ -1,0 +1,1187 @@
+// gfx950 kernels of the PIC step: on-device particle loader, tile sort,
+// gather-push-deposit with in-kernel per-box clock costs, Yee update, and
+// the per-box counts and features used for load balancing.
+//
+// Numerical methods (the paper names the PIC scheme only in words, Sec. 2.1):
+//   shapes   centred B-splines of order 1 or 2;
+//   gather   each component interpolated at its own Yee stagger with the same
+//            order-m spline;
+//   push     relativistic Boris rotation (Boris 1970; Birdsall & Langdon);
+//   deposit  Esirkepov (2001) charge-conserving density decomposition;
+//   fields   Yee (1966): B half step, E full step with -J, B half step.
+// Per-box costs follow Sec. 2.2 and Fig. 2a: a device clock is read around
+// the compute-intensive work, summed on chip, then added once per block to a
+// global per-box counter.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace pb {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int wrap_any(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Wraps a tile-relative coordinate r into [-h, n - h).
+__device__ __forceinline__ int wrap_rel(int r, int h, int n) {
+    int t = r + h;
+    if (t < 0) t += n;
+    else if (t >= n) t -= n;
+    if (t < 0 || t >= n) t = wrap_any(t, n);
+    return t - h;
+}
+
+template <typename real>
+__device__ __forceinline__ void atomic_add_global(real *p, real v) {
+    unsafeAtomicAdd(p, v);
+}
+
+template <typename real>
+__device__ __forceinline__ void atomic_add_lds(real *p, real v) {
+    unsafeAtomicAdd(p, v);
+}
+
+// Exclusive block scan of one int per thread (blockDim a multiple of 64,
+// at most 1024).  sh needs 17 ints.  Returns the exclusive prefix; total is
+// the block sum.
+__device__ int block_excl_scan(int v, int *sh, int &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < nw; ++i) {
+            int t = sh[i];
+            sh[i] = acc;
+            acc += t;
+        }
+        sh[16] = acc;
+    }
+    __syncthreads();
+    int r = x - v + sh[wid];
+    total = sh[16];
+    __syncthreads();
+    return r;
+}
+
+// Adds 1 to arr[key] for every active lane, with one atomic per distinct key
+// in the wave.
+__device__ void wave_count_add(unsigned long long *arr, int key) {
+    unsigned long long active = __ballot(1);
+    while (active) {
+        int leader = __ffsll((long long)active) - 1;
+        int lkey = __shfl(key, leader);
+        unsigned long long same = __ballot(key == lkey) & active;
+        if (key == lkey && (int)__lane_id() == leader)
+            atomicAdd(&arr[key], (unsigned long long)__popcll(same));
+        active &= ~same;
+    }
+}
+
+__device__ void wave_sum_add(double *arr, int key, double v) {
+    unsigned long long active = __ballot(1);
+    while (active) {
+        int leader = __ffsll((long long)active) - 1;
+        int lkey = __shfl(key, leader);
+        bool mine = key == lkey;
+        unsigned long long same = __ballot(mine) & active;
+        double s = mine ? v : 0.0;
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (mine && (int)__lane_id() == leader) atomicAdd(&arr[key], s);
+        active &= ~same;
+    }
+}
+
+// Box, tile and cell-in-tile of global cell (x, y, z).
+__device__ __forceinline__ void locate(const Geom &G, int x, int y, int z, int &box, int &tile,
+                                       int &local) {
+    int b = G.coarse_box[(x / G.g[0]) + G.cg[0] * ((y / G.g[1]) + G.cg[1] * (z / G.g[2]))];
+    int lx = x - G.box_lo[3 * b], ly = y - G.box_lo[3 * b + 1], lz = z - G.box_lo[3 * b + 2];
+    int tx = lx / G.T[0], ty = ly / G.T[1], tz = lz / G.T[2];
+    box = b;
+    tile = G.box_tile_off[b] + tx + G.box_nt[3 * b] * (ty + G.box_nt[3 * b + 1] * tz);
+    local = (lx - tx * G.T[0]) + G.T[0] * ((ly - ty * G.T[1]) + G.T[1] * (lz - tz * G.T[2]));
+}
+
+__device__ __forceinline__ int box_of_cell(const Geom &G, int x, int y, int z) {
+    return G.coarse_box[(x / G.g[0]) + G.cg[0] * ((y / G.g[1]) + G.cg[1] * (z / G.g[2]))];
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the particle loader
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        uint32_t n0 = hi1 ^ c[1] ^ k0;
+        uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+template <typename real>
+__global__ void k_load(Particles<real> P, LoadArgs a) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    int cx, cy, cz;
+    double w;
+    if (a.mode == 1) {
+        int64_t cellrank = p / a.ppc;
+        cx = a.rlo[0] + (int)(cellrank % a.rext[0]);
+        int64_t q = cellrank / a.rext[0];
+        cy = a.rlo[1] + (int)(q % a.rext[1]);
+        cz = a.rlo[2] + (int)(q / a.rext[1]);
+        w = a.density / (double)a.ppc;
+    } else {
+        // box b with base[b] <= p < base[b+1]
+        int lo = 0, hi = a.nb;  // base has nb+1 entries
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (a.box_base[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        int b = lo;
+        int ppc = a.box_ppc[b];
+        int64_t local = (p - a.box_base[b]) / ppc;
+        const int *bx = a.boxes6 + 6 * b;
+        int ex = bx[3] - bx[0], ey = bx[4] - bx[1];
+        cx = bx[0] + (int)(local % ex);
+        cy = bx[1] + (int)((local / ex) % ey);
+        cz = bx[2] + (int)(local / ((int64_t)ex * ey));
+        w = a.density / (double)ppc;
+    }
+    uint32_t lo32 = (uint32_t)(uint64_t)p, hi32 = (uint32_t)((uint64_t)p >> 32);
+    uint32_t r0[4] = {lo32, hi32, 0u, 0u}, r1[4] = {lo32, hi32, 1u, 0u};
+    philox4x32_10(r0, a.k0, a.k1);
+    philox4x32_10(r1, a.k0, a.k1);
+    const double s24 = 1.0 / 16777216.0;
+    double U0 = (double)(r0[0] >> 8) * s24, U1 = (double)(r0[1] >> 8) * s24, U2 = (double)(r0[2] >> 8) * s24;
+    double ga = ((double)(r0[3] >> 8) + 1.0) * s24, gb = (double)(r1[0] >> 8) * s24;
+    double gc = ((double)(r1[1] >> 8) + 1.0) * s24, ge = (double)(r1[2] >> 8) * s24;
+    const double twopi = 6.283185307179586476925286766559;
+    double ra = sqrt(-2.0 * log(ga)), rc = sqrt(-2.0 * log(gc));
+    double n0 = ra * cos(twopi * gb), n1 = ra * sin(twopi * gb), n2 = rc * cos(twopi * ge);
+    int64_t d = a.out_base + p;
+    P.cell[d] = pack_cell(cx, cy, cz);
+    P.f[0][d] = (real)U0;
+    P.f[1][d] = (real)U1;
+    P.f[2][d] = (real)U2;
+    P.u[0][d] = (real)(a.uth[0] * n0 + a.udrift[0]);
+    P.u[1][d] = (real)(a.uth[1] * n1 + a.udrift[1]);
+    P.u[2][d] = (real)(a.uth[2] * n2 + a.udrift[2]);
+    P.w[d] = (real)w;
+    P.id[d] = p;
+    P.sp[d] = (uint8_t)a.species;
+}
+
+// ---------------------------------------------------------------------------
+// Tile sort.  Output order: by (tile, species), and inside a (tile, species)
+// segment by (rank of the particle within its cell, cell).  Consecutive
+// particles then sit in distinct cells, so the lanes of a wave deposit into
+// distinct LDS addresses.  For quadratic shapes the "cell" is the nearest
+// node, which fixes the start of the particle's deposit window.
+// ---------------------------------------------------------------------------
+
+template <typename real>
+__device__ __forceinline__ void sort_cell(const Particles<real> &P, const Geom &G, int p, int &x, int &y,
+                                          int &z) {
+    unpack_cell(P.cell[p], x, y, z);
+    if (G.order == 2) {
+        x += P.f[0][p] >= (real)0.5;
+        y += P.f[1][p] >= (real)0.5;
+        z += P.f[2][p] >= (real)0.5;
+        if (x == G.n[0]) x = 0;
+        if (y == G.n[1]) y = 0;
+        if (z == G.n[2]) z = 0;
+    }
+}
+
+template <typename real>
+__global__ void k_sort_key(Particles<real> P, int np, Geom G, uint32_t *cellcnt, uint32_t *key,
+                           uint32_t *rank) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    int x, y, z, b, t, l;
+    sort_cell(P, G, p, x, y, z);
+    locate(G, x, y, z, b, t, l);
+    uint32_t k = (uint32_t)((t * G.nsp + P.sp[p]) * G.Tvol + l);
+    key[p] = k;
+    rank[p] = atomicAdd(&cellcnt[k], 1u);
+}
+
+__global__ void k_sort_seg(const uint32_t *cellcnt, uint32_t *cellstart, int *segtot, int Tvol) {
+    __shared__ int sh[17];
+    int ts = blockIdx.x;
+    int v = (int)cellcnt[(size_t)ts * Tvol + threadIdx.x];
+    int tot;
+    int ex = block_excl_scan(v, sh, tot);
+    cellstart[(size_t)ts * Tvol + threadIdx.x] = (uint32_t)ex;
+    if (threadIdx.x == 0) segtot[ts] = tot;
+}
+
+// Exclusive scan of n ints into out[0..n] (out[n] = total); one block.
+__global__ void k_scan_single(const int *in, int *out, int n) {
+    __shared__ int sh[17];
+    int per = (n + blockDim.x - 1) / blockDim.x;
+    int b = threadIdx.x * per, e = min(n, b + per);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += in[i];
+    int tot;
+    int ex = block_excl_scan(s, sh, tot);
+    for (int i = b; i < e; ++i) {
+        out[i] = ex;
+        ex += in[i];
+    }
+    if (threadIdx.x == 0) out[n] = tot;
+}
+
+__global__ void k_sort_levels(const uint32_t *cellcnt, const uint32_t *cellstart, const int *segstart,
+                              uint32_t *table, int Tvol) {
+    __shared__ int sh[17];
+    __shared__ int smax;
+    int ts = blockIdx.x;
+    int base = segstart[ts];
+    if (segstart[ts + 1] == base) return;
+    size_t ci = (size_t)ts * Tvol + threadIdx.x;
+    int cnt = (int)cellcnt[ci];
+    int cs = (int)cellstart[ci];
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    atomicMax(&smax, cnt);
+    __syncthreads();
+    int maxc = smax;
+    int lvl = 0;
+    for (int k = 0; k < maxc; ++k) {
+        int flag = cnt > k;
+        int tot;
+        int r = block_excl_scan(flag, sh, tot);
+        if (flag) table[base + cs + k] = (uint32_t)(base + lvl + r);
+        lvl += tot;
+    }
+}
+
+template <typename real>
+__global__ void k_sort_scatter(Particles<real> S, Particles<real> D, int np, const uint32_t *key,
+                               const uint32_t *rank, const uint32_t *cellstart, const int *segstart,
+                               const uint32_t *table, int Tvol) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    uint32_t k = key[p];
+    int ts = (int)(k / (uint32_t)Tvol);
+    int idx = segstart[ts] + (int)cellstart[k] + (int)rank[p];
+    int d = (int)table[idx];
+    D.cell[d] = S.cell[p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        D.f[c][d] = S.f[c][p];
+        D.u[c][d] = S.u[c][p];
+    }
+    D.w[d] = S.w[p];
+    D.id[d] = S.id[p];
+    D.sp[d] = S.sp[p];
+}
+
+// ---------------------------------------------------------------------------
+// Work queue for the persistent kernel: tiles cut into chunks of at most
+// `chunk` particles, ordered largest first (size classes).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int size_class(int sz, int chunk, int ncls) {
+    int c = (int)(((long long)(chunk - sz) * ncls) / chunk);
+    return c < 0 ? 0 : (c >= ncls ? ncls - 1 : c);
+}
+
+__global__ void k_queue_count(const int *segstart, int ntiles, int nsp, int chunk, int ncls, int *cls_cnt) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int n = segstart[(t + 1) * nsp] - segstart[t * nsp];
+    if (n == 0) return;
+    int full = n / chunk, rem = n - full * chunk;
+    if (full) atomicAdd(&cls_cnt[0], full);
+    if (rem) atomicAdd(&cls_cnt[size_class(rem, chunk, ncls)], 1);
+}
+
+__global__ void k_queue_scan(int *cls_cnt, int *cursor, int ncls, int *queue_len) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int acc = 0;
+    for (int c = 0; c < ncls; ++c) {
+        cursor[c] = acc;
+        acc += cls_cnt[c];
+        cls_cnt[c] = 0;
+    }
+    *queue_len = acc;
+}
+
+__global__ void k_queue_fill(const int *segstart, int ntiles, int nsp, int chunk, int ncls, int *cursor,
+                             int4 *queue) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int b = segstart[t * nsp], n = segstart[(t + 1) * nsp] - b;
+    if (n == 0) return;
+    int full = n / chunk, rem = n - full * chunk;
+    if (full) {
+        int pos = atomicAdd(&cursor[0], full);
+        for (int j = 0; j < full; ++j) queue[pos + j] = make_int4(t, b + j * chunk, b + (j + 1) * chunk, 0);
+    }
+    if (rem) {
+        int pos = atomicAdd(&cursor[size_class(rem, chunk, ncls)], 1);
+        queue[pos] = make_int4(t, b + full * chunk, b + n, 0);
+    }
+}
+
+__global__ void k_set_int(int *p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+template <typename T>
+__global__ void k_fill(T *a, T v, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Gather - push - deposit
+// ---------------------------------------------------------------------------
+
+// Compile-time tile configuration.  Positions are referred to the particle's
+// cell (order 1) or nearest node (order 2); the staged E/B window reaches
+// RL_EB below and RH_EB above it, the J window RL_J / RH_J, plus the tile
+// halo H on both sides.
+template <typename real, int M, int TX, int TY, int TZ, int H>
+struct Cfg {
+    static constexpr int RL_EB = (M == 2) ? 2 : 1, RH_EB = 1;
+    static constexpr int RL_J = (M == 2) ? 2 : 1, RH_J = 2;
+    static constexpr int EX = TX + 2 * H + RL_EB + RH_EB;
+    static constexpr int EY = TY + 2 * H + RL_EB + RH_EB;
+    static constexpr int EZ = TZ + 2 * H + RL_EB + RH_EB;
+    static constexpr int JX = TX + 2 * H + RL_J + RH_J;
+    static constexpr int JY = TY + 2 * H + RL_J + RH_J;
+    static constexpr int JZ = TZ + 2 * H + RL_J + RH_J;
+    static constexpr int NEB = EX * EY * EZ;
+    static constexpr int NJ = JX * JY * JZ;
+    static constexpr size_t lds = (size_t)(6 * NEB + 3 * NJ) * sizeof(real);
+};
+
+// Shape factors of one dimension.  Inputs: d = offset from the reference
+// (order 1: cell offset f in [0,1); order 2: node offset in [-1/2, 1/2)).
+// Gather weights at integer nodes (wn, first node at offset bn) and at half
+// nodes (wh, first half node at offset bh, dynamic).
+template <typename real, int M>
+struct GatherW {
+    real wn[M + 1], wh[M + 1];
+    int bh;
+    __device__ __forceinline__ void set(real d) {
+        if (M == 1) {
+            wn[0] = (real)1 - d;
+            wn[1] = d;
+            bool up = d >= (real)0.5;
+            real t = up ? d - (real)0.5 : d + (real)0.5;
+            bh = up ? 0 : -1;
+            wh[0] = (real)1 - t;
+            wh[1] = t;
+        } else {
+            const real h = (real)0.5;
+            wn[0] = h * (h - d) * (h - d);
+            wn[1] = (real)0.75 - d * d;
+            wn[2] = h * (h + d) * (h + d);
+            bool up = d >= (real)0;
+            real t = up ? d - h : d + h;
+            bh = up ? -1 : -2;
+            wh[0] = h * (h - t) * (h - t);
+            wh[1] = (real)0.75 - t * t;
+            wh[2] = h * (h + t) * (h + t);
+        }
+    }
+};
+
+// Esirkepov window of one dimension: (M+2) nodes starting at offset s from
+// the reference; S0 = old shape, dS = new - old shape.  When the particle
+// keeps its reference node the differences are formed from the
+// displacement itself (no cancellation).
+template <typename real, int M>
+struct DepW {
+    real S0[M + 2], dS[M + 2];
+    int s;
+    __device__ __forceinline__ void set(real d0, real D) {
+        real d1 = d0 + D;
+        if (M == 1) {
+            int k = (d1 >= (real)1) - (d1 < (real)0);
+            real f1 = d1 - (real)k;
+            bool km = k < 0, kp = k > 0;
+            real a0 = (real)1 - d0, b0 = d0;
+            real a1 = (real)1 - f1, b1 = f1;
+            S0[0] = km ? (real)0 : a0;
+            S0[1] = km ? a0 : b0;
+            S0[2] = km ? b0 : (real)0;
+            real s10 = kp ? (real)0 : a1;
+            real s11 = kp ? a1 : b1;
+            real s12 = kp ? b1 : (real)0;
+            dS[0] = s10 - S0[0];
+            dS[1] = s11 - S0[1];
+            dS[2] = s12 - S0[2];
+            if (k == 0) {
+                dS[0] = -D;
+                dS[1] = D;
+                dS[2] = (real)0;
+            }
+            s = km ? -1 : 0;
+        } else {
+            const real h = (real)0.5;
+            int k = (d1 >= h) - (d1 < -h);
+            real e = d1 - (real)k;
+            bool km = k < 0, kp = k > 0;
+            real A0 = h * (h - d0) * (h - d0), B0 = (real)0.75 - d0 * d0, C0 = h * (h + d0) * (h + d0);
+            real A1 = h * (h - e) * (h - e), B1 = (real)0.75 - e * e, C1 = h * (h + e) * (h + e);
+            S0[0] = km ? (real)0 : A0;
+            S0[1] = km ? A0 : B0;
+            S0[2] = km ? B0 : C0;
+            S0[3] = km ? C0 : (real)0;
+            real s1[4];
+            s1[0] = kp ? (real)0 : A1;
+            s1[1] = kp ? A1 : B1;
+            s1[2] = kp ? B1 : C1;
+            s1[3] = kp ? C1 : (real)0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) dS[a] = s1[a] - S0[a];
+            if (k == 0) {
+                real sg = d0 + d1;
+                dS[0] = -h * D * ((real)1 - sg);
+                dS[1] = -D * sg;
+                dS[2] = h * D * ((real)1 + sg);
+                dS[3] = (real)0;
+            }
+            s = km ? -2 : -1;
+        }
+    }
+};
+
+// Interpolates the six field components from an accessor F(comp, i, j, k)
+// where (i,j,k) are offsets from the particle's reference.
+template <typename real, int M, typename Acc>
+__device__ __forceinline__ void gather6(const Acc &F, const GatherW<real, M> W[3], real EB[6]) {
+    const int bn = (M == 2) ? -1 : 0;
+    // stagger pattern per component: 1 = half node along that axis
+    const int pat[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const real *wx = pat[c][0] ? W[0].wh : W[0].wn;
+        const real *wy = pat[c][1] ? W[1].wh : W[1].wn;
+        const real *wz = pat[c][2] ? W[2].wh : W[2].wn;
+        int ox = pat[c][0] ? W[0].bh : bn;
+        int oy = pat[c][1] ? W[1].bh : bn;
+        int oz = pat[c][2] ? W[2].bh : bn;
+        real acc = (real)0;
+        F.begin(c, ox, oy, oz);
+#pragma unroll
+        for (int k = 0; k <= M; ++k) {
+            real ay = (real)0;
+#pragma unroll
+            for (int j = 0; j <= M; ++j) {
+                real ax = (real)0;
+#pragma unroll
+                for (int i = 0; i <= M; ++i) ax += wx[i] * F.tap(i, j, k);
+                ay += wy[j] * ax;
+            }
+            acc += wz[k] * ay;
+        }
+        EB[c] = acc;
+    }
+}
+
+// Deposits the Esirkepov current through an accessor J.add(comp, a, b, c, v)
+// with (a,b,c) offsets inside the window.
+template <typename real, int M, typename Acc>
+__device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real coef) {
+    constexpr int L = M + 2;
+    const real h = (real)0.5, third = (real)(1.0 / 3.0);
+    J.begin(W[0].s, W[1].s, W[2].s);
+    // Jx: running sum along x
+#pragma unroll
+    for (int c = 0; c < L; ++c)
+#pragma unroll
+        for (int b = 0; b < L; ++b) {
+            real in = W[1].S0[b] * W[2].S0[c] + h * (W[1].dS[b] * W[2].S0[c] + W[1].S0[b] * W[2].dS[c]) +
+                      third * W[1].dS[b] * W[2].dS[c];
+            real acc = (real)0;
+#pragma unroll
+            for (int a = 0; a < L - 1; ++a) {
+                acc += W[0].dS[a] * in;
+                J.add(0, a, b, c, coef * acc);
+            }
+        }
+    // Jy: running sum along y
+#pragma unroll
+    for (int c = 0; c < L; ++c)
+#pragma unroll
+        for (int a = 0; a < L; ++a) {
+            real in = W[0].S0[a] * W[2].S0[c] + h * (W[0].dS[a] * W[2].S0[c] + W[0].S0[a] * W[2].dS[c]) +
+                      third * W[0].dS[a] * W[2].dS[c];
+            real acc = (real)0;
+#pragma unroll
+            for (int b = 0; b < L - 1; ++b) {
+                acc += W[1].dS[b] * in;
+                J.add(1, a, b, c, coef * acc);
+            }
+        }
+    // Jz: running sum along z
+#pragma unroll
+    for (int b = 0; b < L; ++b)
+#pragma unroll
+        for (int a = 0; a < L; ++a) {
+            real in = W[0].S0[a] * W[1].S0[b] + h * (W[0].dS[a] * W[1].S0[b] + W[0].S0[a] * W[1].dS[b]) +
+                      third * W[0].dS[a] * W[1].dS[b];
+            real acc = (real)0;
+#pragma unroll
+            for (int c = 0; c < L - 1; ++c) {
+                acc += W[2].dS[c] * in;
+                J.add(2, a, b, c, coef * acc);
+            }
+        }
+}
+
+// Accessors: staged LDS windows (compile-time strides) ...
+template <typename real, typename C>
+struct LdsEB {
+    const real *s;
+    int ref;  // linear LDS index of the reference node (component 0)
+    mutable int base;
+    __device__ __forceinline__ void begin(int c, int ox, int oy, int oz) const {
+        base = c * C::NEB + ref + ox + C::EX * (oy + C::EY * oz);
+    }
+    __device__ __forceinline__ real tap(int i, int j, int k) const {
+        return s[base + i + C::EX * (j + C::EY * k)];
+    }
+};
+
+template <typename real, typename C>
+struct LdsJ {
+    real *s;
+    int ref;
+    int base;
+    __device__ __forceinline__ void begin(int sx, int sy, int sz) {
+        base = ref + sx + C::JX * (sy + C::JY * sz);
+    }
+    __device__ __forceinline__ void add(int comp, int a, int b, int c, real v) {
+        atomic_add_lds(&s[comp * C::NJ + base + a + C::JX * (b + C::JY * c)], v);
+    }
+};
+
+// ... and global arrays with periodic wrap (particles beyond the halo).
+template <typename real>
+struct GlobEB {
+    const real *const *EB;
+    int n[3], r[3];
+    mutable const real *arr;
+    mutable int ix[3], iy[3], iz[3];
+    __device__ __forceinline__ void begin(int c, int ox, int oy, int oz) const {
+        arr = EB[c];
+        for (int q = 0; q < 3; ++q) {
+            ix[q] = wrap_any(r[0] + ox + q, n[0]);
+            iy[q] = wrap_any(r[1] + oy + q, n[1]);
+            iz[q] = wrap_any(r[2] + oz + q, n[2]);
+        }
+    }
+    __device__ __forceinline__ real tap(int i, int j, int k) const {
+        return arr[ix[i] + (size_t)n[0] * (iy[j] + (size_t)n[1] * iz[k])];
+    }
+};
+
+template <typename real>
+struct GlobJ {
+    real *const *J;
+    int n[3], r[3];
+    int ix[4], iy[4], iz[4];
+    __device__ __forceinline__ void begin(int sx, int sy, int sz) {
+        for (int q = 0; q < 4; ++q) {
+            ix[q] = wrap_any(r[0] + sx + q, n[0]);
+            iy[q] = wrap_any(r[1] + sy + q, n[1]);
+            iz[q] = wrap_any(r[2] + sz + q, n[2]);
+        }
+    }
+    __device__ __forceinline__ void add(int comp, int a, int b, int c, real v) {
+        atomic_add_global(&J[comp][ix[a] + (size_t)n[0] * (iy[b] + (size_t)n[1] * iz[c])], v);
+    }
+};
+
+template <typename real, int M, int TX, int TY, int TZ, int H>
+__device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, const TileDesc &td, real hq,
+                                              real cq, const real *sEB, real *sJ, unsigned &nslow) {
+    using C = Cfg<real, M, TX, TY, TZ, H>;
+    int c[3];
+    unpack_cell(A.P.cell[p], c[0], c[1], c[2]);
+    real f[3] = {A.P.f[0][p], A.P.f[1][p], A.P.f[2][p]};
+    real u[3] = {A.P.u[0][p], A.P.u[1][p], A.P.u[2][p]};
+    real w = A.P.w[p];
+
+    // reference point: cell (order 1) or nearest node (order 2)
+    int ref[3];
+    real d0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (M == 2) {
+            bool up = f[d] >= (real)0.5;
+            ref[d] = c[d] + (up ? 1 : 0);
+            d0[d] = up ? f[d] - (real)1 : f[d];
+        } else {
+            ref[d] = c[d];
+            d0[d] = f[d];
+        }
+    }
+    const int T[3] = {TX, TY, TZ};
+    const int org[3] = {td.x0, td.y0, td.z0};
+    int rel[3];
+    bool fast = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        rel[d] = wrap_rel(ref[d] - org[d], H, A.n[d]);
+        fast = fast && rel[d] <= T[d] + H - 1;
+    }
+
+    GatherW<real, M> GW[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) GW[d].set(d0[d]);
+    real EB[6];
+    if (fast) {
+        LdsEB<real, C> acc{sEB, (rel[0] + H + C::RL_EB) + C::EX * ((rel[1] + H + C::RL_EB) + C::EY * (rel[2] + H + C::RL_EB)), 0};
+        gather6<real, M>(acc, GW, EB);
+    } else {
+        GlobEB<real> acc;
+        acc.EB = A.EB;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            acc.n[d] = A.n[d];
+            acc.r[d] = ref[d];
+        }
+        gather6<real, M>(acc, GW, EB);
+        ++nslow;
+    }
+    // the arrays hold B minus its uniform external part (whose curl is zero)
+    EB[3] += A.bext[0];
+    EB[4] += A.bext[1];
+    EB[5] += A.bext[2];
+
+    // relativistic Boris rotation
+    real um[3] = {u[0] + hq * EB[0], u[1] + hq * EB[1], u[2] + hq * EB[2]};
+    real ig = (real)1 / sqrt((real)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    real t[3] = {hq * EB[3] * ig, hq * EB[4] * ig, hq * EB[5] * ig};
+    real t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    real sf = (real)2 / ((real)1 + t2);
+    real s[3] = {sf * t[0], sf * t[1], sf * t[2]};
+    real up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]), um[1] + (um[2] * t[0] - um[0] * t[2]),
+                  um[2] + (um[0] * t[1] - um[1] * t[0])};
+    u[0] = um[0] + (up[1] * s[2] - up[2] * s[1]) + hq * EB[0];
+    u[1] = um[1] + (up[2] * s[0] - up[0] * s[2]) + hq * EB[1];
+    u[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + hq * EB[2];
+    real gi = (real)1 / sqrt((real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    real D[3] = {A.dt * u[0] * gi, A.dt * u[1] * gi, A.dt * u[2] * gi};
+
+    // Esirkepov deposit
+    DepW<real, M> DW[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) DW[d].set(d0[d], D[d]);
+    real coef = cq * w;
+    if (fast) {
+        LdsJ<real, C> acc{sJ, (rel[0] + H + C::RL_J) + C::JX * ((rel[1] + H + C::RL_J) + C::JY * (rel[2] + H + C::RL_J)), 0};
+        deposit3<real, M>(acc, DW, coef);
+    } else {
+        GlobJ<real> acc;
+        acc.J = A.J;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            acc.n[d] = A.n[d];
+            acc.r[d] = ref[d];
+        }
+        deposit3<real, M>(acc, DW, coef);
+    }
+
+    // new canonical position: cell + offset in [0, 1), periodic wrap
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        real x = f[d] + D[d];
+        int k = 0;
+        if (x < (real)0) {
+            x += (real)1;
+            k = -1;
+            if (x >= (real)1) {
+                x = (real)0;
+                k = 0;
+            }
+        } else if (x >= (real)1) {
+            x -= (real)1;
+            k = 1;
+        }
+        int cc = c[d] + k;
+        if (cc < 0) cc += A.n[d];
+        else if (cc >= A.n[d]) cc -= A.n[d];
+        c[d] = cc;
+        f[d] = x;
+    }
+    A.P.cell[p] = pack_cell(c[0], c[1], c[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        A.P.f[d][p] = f[d];
+        A.P.u[d][p] = u[d];
+    }
+}
+
+template <typename real, int M, int TX, int TY, int TZ, int H>
+__global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
+    using C = Cfg<real, M, TX, TY, TZ, H>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    real *sEB = reinterpret_cast<real *>(smem_raw);
+    real *sJ = sEB + 6 * C::NEB;
+    __shared__ unsigned long long sCyc, sRtc;
+    __shared__ unsigned int sSlow;
+    __shared__ int sItem[3];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int nsp = A.nsp;
+
+    for (int iter = 0;; ++iter) {
+        int tile, pbeg, pend;
+        if (A.mode == MODE_PERSISTENT) {
+            if (tid == 0) {
+                int q = atomicAdd(A.queue_head, 1);
+                if (q < *A.queue_len) {
+                    int4 it = A.queue[q];
+                    sItem[0] = it.x;
+                    sItem[1] = it.y;
+                    sItem[2] = it.z;
+                } else {
+                    sItem[0] = -1;
+                }
+            }
+            __syncthreads();
+            tile = sItem[0];
+            pbeg = sItem[1];
+            pend = sItem[2];
+            if (tile < 0) break;
+        } else {
+            if (iter > 0) break;
+            tile = A.tile_base + blockIdx.x;
+            if (A.species_only >= 0) {
+                pbeg = A.segstart[tile * nsp + A.species_only];
+                pend = A.segstart[tile * nsp + A.species_only + 1];
+            } else {
+                pbeg = A.segstart[tile * nsp];
+                pend = A.segstart[(tile + 1) * nsp];
+            }
+            if (pbeg >= pend) break;
+        }
+        const TileDesc td = A.tiles[tile];
+
+        // stage E and B of the tile window; clear the J window
+        for (int i = tid; i < 6 * C::NEB; i += nthr) {
+            int comp = i / C::NEB;
+            int r = i - comp * C::NEB;
+            int lx = r % C::EX;
+            int r2 = r / C::EX;
+            int ly = r2 % C::EY;
+            int lz = r2 / C::EY;
+            int gx = wrap_any(td.x0 - H - C::RL_EB + lx, A.n[0]);
+            int gy = wrap_any(td.y0 - H - C::RL_EB + ly, A.n[1]);
+            int gz = wrap_any(td.z0 - H - C::RL_EB + lz, A.n[2]);
+            sEB[i] = A.EB[comp][gx + (size_t)A.n[0] * (gy + (size_t)A.n[1] * gz)];
+        }
+        for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = (real)0;
+        if (tid == 0) {
+            sCyc = 0;
+            sRtc = 0;
+            sSlow = 0;
+        }
+        __syncthreads();
+
+        unsigned long long c0 = clock64(), r0 = wall_clock64();
+        unsigned nslow = 0;
+        for (int s = 0; s < nsp; ++s) {
+            if (A.mode == MODE_PER_BOX && s != A.species_only) continue;
+            int sb = max(pbeg, A.segstart[tile * nsp + s]);
+            int se = min(pend, A.segstart[tile * nsp + s + 1]);
+            real hq = A.h[s], cq = A.coefq[s];
+            for (int p = sb + tid; p < se; p += nthr)
+                push_particle<real, M, TX, TY, TZ, H>(A, p, td, hq, cq, sEB, sJ, nslow);
+        }
+        unsigned long long c1 = clock64(), r1 = wall_clock64();
+        if ((tid & 63) == 0) {
+            atomicAdd(&sCyc, c1 - c0);
+            atomicAdd(&sRtc, r1 - r0);
+        }
+        if (nslow) atomicAdd(&sSlow, nslow);
+        __syncthreads();
+
+        // flush the J window
+        for (int i = tid; i < 3 * C::NJ; i += nthr) {
+            real v = sJ[i];
+            if (v != (real)0) {
+                int comp = i / C::NJ;
+                int r = i - comp * C::NJ;
+                int lx = r % C::JX;
+                int r2 = r / C::JX;
+                int ly = r2 % C::JY;
+                int lz = r2 / C::JY;
+                int gx = wrap_any(td.x0 - H - C::RL_J + lx, A.n[0]);
+                int gy = wrap_any(td.y0 - H - C::RL_J + ly, A.n[1]);
+                int gz = wrap_any(td.z0 - H - C::RL_J + lz, A.n[2]);
+                atomic_add_global(&A.J[comp][gx + (size_t)A.n[0] * (gy + (size_t)A.n[1] * gz)], v);
+            }
+        }
+        if (tid == 0) {
+            atomicAdd(&A.cycles[td.box], sCyc);
+            atomicAdd(&A.rtc[td.box], sRtc);
+            if (sSlow) atomicAdd(A.slow, sSlow);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Yee update
+// ---------------------------------------------------------------------------
+
+template <typename real>
+__global__ void k_yee_b(real *Bx, real *By, real *Bz, const real *Ex, const real *Ey, const real *Ez, int nx,
+                        int ny, int nz, real hdt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y, k = blockIdx.z;
+    if (i >= nx) return;
+    int ip = i + 1 == nx ? 0 : i + 1, jp = j + 1 == ny ? 0 : j + 1, kp = k + 1 == nz ? 0 : k + 1;
+    size_t sy = nx, sz = (size_t)nx * ny;
+    size_t c = i + sy * j + sz * k;
+    size_t cxp = ip + sy * j + sz * k, cyp = i + sy * jp + sz * k, czp = i + sy * j + sz * kp;
+    real ex = Ex[c], ey = Ey[c], ez = Ez[c];
+    real cx = (Ez[cyp] - ez) - (Ey[czp] - ey);
+    real cy = (Ex[czp] - ex) - (Ez[cxp] - ez);
+    real cz = (Ey[cxp] - ey) - (Ex[cyp] - ex);
+    Bx[c] -= hdt * cx;
+    By[c] -= hdt * cy;
+    Bz[c] -= hdt * cz;
+}
+
+template <typename real>
+__global__ void k_yee_e(real *Ex, real *Ey, real *Ez, const real *Bx, const real *By, const real *Bz,
+                        const real *Jx, const real *Jy, const real *Jz, real *Zx, real *Zy, real *Zz, int nx,
+                        int ny, int nz, real dt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y, k = blockIdx.z;
+    if (i >= nx) return;
+    int im = i == 0 ? nx - 1 : i - 1, jm = j == 0 ? ny - 1 : j - 1, km = k == 0 ? nz - 1 : k - 1;
+    size_t sy = nx, sz = (size_t)nx * ny;
+    size_t c = i + sy * j + sz * k;
+    size_t cxm = im + sy * j + sz * k, cym = i + sy * jm + sz * k, czm = i + sy * j + sz * km;
+    real bx = Bx[c], by = By[c], bz = Bz[c];
+    real cx = (bz - Bz[cym]) - (by - By[czm]);
+    real cy = (bx - Bx[czm]) - (bz - Bz[cxm]);
+    real cz = (by - By[cxm]) - (bx - Bx[cym]);
+    Ex[c] += dt * (cx - Jx[c]);
+    Ey[c] += dt * (cy - Jy[c]);
+    Ez[c] += dt * (cz - Jz[c]);
+    // clear the other J buffer for the next step's deposit
+    Zx[c] = (real)0;
+    Zy[c] = (real)0;
+    Zz[c] = (real)0;
+}
+
+// ---------------------------------------------------------------------------
+// Per-box counts and features
+// ---------------------------------------------------------------------------
+
+template <typename real>
+__global__ void k_box_counts(Particles<real> P, int np, Geom G, unsigned long long *counts) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    int x, y, z;
+    unpack_cell(P.cell[p], x, y, z);
+    int b = box_of_cell(G, x, y, z);
+    wave_count_add(counts, b * G.nsp + P.sp[p]);
+}
+
+// Per-particle pass of the features: per-cell counts, per-box species counts,
+// outer-layer counts and the sum of |u|.
+template <typename real>
+__global__ void k_feat_particles(Particles<real> P, int np, Geom G, const int *box_hi, uint32_t *cellcount,
+                                 unsigned long long *spcnt, unsigned long long *edge, double *usum) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    int x, y, z;
+    unpack_cell(P.cell[p], x, y, z);
+    int b = box_of_cell(G, x, y, z);
+    atomicAdd(&cellcount[x + (size_t)G.n[0] * (y + (size_t)G.n[1] * z)], 1u);
+    int s = P.sp[p];
+    if (s < 2) wave_count_add(spcnt, 2 * b + s);
+    const int *lo = G.box_lo + 3 * b, *hi = box_hi + 3 * b;
+    bool on = x == lo[0] || x == hi[0] - 1 || y == lo[1] || y == hi[1] - 1 || z == lo[2] || z == hi[2] - 1;
+    if (on) wave_count_add(edge, b);
+    double ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
+    wave_sum_add(usum, b, sqrt(ux * ux + uy * uy + uz * uz));
+}
+
+__global__ void k_feat_boxes(const uint32_t *cellcount, Geom G, const int *box_hi, const unsigned long long *spcnt,
+                             const unsigned long long *edge, const double *usum, float *feat) {
+    __shared__ unsigned int hist[8];
+    __shared__ unsigned int smax;
+    int b = blockIdx.x;
+    if (threadIdx.x < 8) hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    const int *lo = G.box_lo + 3 * b, *hi = box_hi + 3 * b;
+    int ex = hi[0] - lo[0], ey = hi[1] - lo[1], ez = hi[2] - lo[2];
+    int ncell = ex * ey * ez;
+    unsigned int lh[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned int lmax = 0;
+    for (int q = threadIdx.x; q < ncell; q += blockDim.x) {
+        int x = lo[0] + q % ex, y = lo[1] + (q / ex) % ey, z = lo[2] + q / (ex * ey);
+        unsigned int v = cellcount[x + (size_t)G.n[0] * (y + (size_t)G.n[1] * z)];
+        int bin = v == 0 ? 0 : (v == 1 ? 1 : min(7, 31 - __clz(v) + 1));
+        // v in [2,3] -> 2, [4,7] -> 3, ... [64, inf) -> 7
+        lh[bin] += 1;
+        lmax = max(lmax, v);
+    }
+    for (int i = 0; i < 8; ++i)
+        if (lh[i]) atomicAdd(&hist[i], lh[i]);
+    atomicMax(&smax, lmax);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float *f = feat + 16 * (size_t)b;
+        double n0 = (double)spcnt[2 * b], n1 = (double)spcnt[2 * b + 1];
+        f[0] = (float)log1p(n0);
+        f[1] = (float)log1p(n1);
+        for (int i = 0; i < 8; ++i) f[2 + i] = (float)log1p((double)hist[i]);
+        f[10] = (float)log((double)ncell);
+        f[11] = (float)G.order;
+        bool touch = lo[0] == 0 || lo[1] == 0 || lo[2] == 0 || hi[0] == G.n[0] || hi[1] == G.n[1] || hi[2] == G.n[2];
+        f[12] = touch ? 1.f : 0.f;
+        f[13] = (float)log1p((double)edge[b]);
+        f[14] = (float)log1p((double)smax);
+        double tot = n0 + n1;
+        f[15] = tot > 0 ? (float)(usum[b] / tot) : 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+template <typename real>
+static Particles<real> cast(const ParticlesRaw &r) {
+    Particles<real> p;
+    p.cell = r.cell;
+    for (int d = 0; d < 3; ++d) {
+        p.f[d] = (real *)r.f[d];
+        p.u[d] = (real *)r.u[d];
+    }
+    p.w = (real *)r.w;
+    p.id = r.id;
+    p.sp = r.sp;
+    return p;
+}
+
+static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_load(int prec, const ParticlesRaw &P, const LoadArgs &a, hipStream_t st) {
+    if (a.n <= 0) return hipSuccess;
+    if (prec == 8) k_load<double><<<nblk(a.n, 256), 256, 0, st>>>(cast<double>(P), a);
+    else k_load<float><<<nblk(a.n, 256), 256, 0, st>>>(cast<float>(P), a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, int np, const Geom &G,
+                       const SortScratch &W, hipStream_t st) {
+    int nts = W.nseg;
+    size_t ncells = (size_t)nts * G.Tvol;
+    k_fill<uint32_t><<<std::min<size_t>(4096, (ncells + 255) / 256), 256, 0, st>>>(W.cellcnt, 0u, ncells);
+    if (np > 0) {
+        if (prec == 8) k_sort_key<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(S), np, G, W.cellcnt, W.key, W.rank);
+        else k_sort_key<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(S), np, G, W.cellcnt, W.key, W.rank);
+    }
+    k_sort_seg<<<nts, G.Tvol, 0, st>>>(W.cellcnt, W.cellstart, W.segtot, G.Tvol);
+    k_scan_single<<<1, 1024, 0, st>>>(W.segtot, W.segstart, nts);
+    k_sort_levels<<<nts, G.Tvol, 0, st>>>(W.cellcnt, W.cellstart, W.segstart, W.table, G.Tvol);
+    if (np > 0) {
+        if (prec == 8)
+            k_sort_scatter<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(S), cast<double>(D), np, W.key, W.rank,
+                                                                   W.cellstart, W.segstart, W.table, G.Tvol);
+        else
+            k_sort_scatter<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(S), cast<float>(D), np, W.key, W.rank,
+                                                                 W.cellstart, W.segstart, W.table, G.Tvol);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_queue(const int *segstart, int ntiles, int nsp, int chunk, const QueueScratch &Q, hipStream_t st) {
+    k_queue_count<<<nblk(ntiles, 256), 256, 0, st>>>(segstart, ntiles, nsp, chunk, Q.ncls, Q.cls_cnt);
+    k_queue_scan<<<1, 64, 0, st>>>(Q.cls_cnt, Q.cursor, Q.ncls, Q.queue_len);
+    k_queue_fill<<<nblk(ntiles, 256), 256, 0, st>>>(segstart, ntiles, nsp, chunk, Q.ncls, Q.cursor, Q.queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_int(int *p, int v, hipStream_t st) {
+    k_set_int<<<1, 64, 0, st>>>(p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f(int prec, void *a, double v, size_t n, hipStream_t st) {
+    unsigned g = (unsigned)std::min<size_t>(8192, (n + 255) / 256);
+    if (g == 0) return hipSuccess;
+    if (prec == 8) k_fill<double><<<g, 256, 0, st>>>((double *)a, v, n);
+    else k_fill<float><<<g, 256, 0, st>>>((float *)a, (float)v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *a, size_t n, hipStream_t st) {
+    unsigned g = (unsigned)std::min<size_t>(8192, (n + 255) / 256);
+    if (g == 0) return hipSuccess;
+    k_fill<unsigned long long><<<g, 256, 0, st>>>(a, 0ull, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st) {
+    unsigned g = (unsigned)std::min<size_t>(8192, (n + 255) / 256);
+    if (g == 0) return hipSuccess;
+    k_fill<uint32_t><<<g, 256, 0, st>>>(a, 0u, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *a, size_t n, hipStream_t st) {
+    unsigned g = (unsigned)std::min<size_t>(8192, (n + 255) / 256);
+    if (g == 0) return hipSuccess;
+    k_fill<double><<<g, 256, 0, st>>>(a, 0.0, n);
+    return hipGetLastError();
+}
+
+// Table of compiled gather-push-deposit variants.
+template <typename real, int M, int TX, int TY, int TZ, int H>
+static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
+    using C = Cfg<real, M, TX, TY, TZ, H>;
+    auto kern = k_gpd<real, M, TX, TY, TZ, H>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    GpdArgs<real> A;
+    A.P = cast<real>(L.P);
+    A.segstart = L.segstart;
+    A.tiles = L.tiles;
+    for (int c = 0; c < 6; ++c) A.EB[c] = (const real *)L.EB[c];
+    for (int c = 0; c < 3; ++c) A.J[c] = (real *)L.J[c];
+    for (int d = 0; d < 3; ++d) A.n[d] = L.n[d];
+    A.nsp = L.nsp;
+    A.dt = (real)L.dt;
+    for (int d = 0; d < 3; ++d) A.bext[d] = (real)L.bext[d];
+    for (int s = 0; s < kMaxSpecies; ++s) {
+        A.h[s] = (real)L.h[s];
+        A.coefq[s] = (real)L.coefq[s];
+    }
+    A.cycles = L.cycles;
+    A.rtc = L.rtc;
+    A.slow = L.slow;
+    A.mode = L.mode;
+    A.tile_base = L.tile_base;
+    A.species_only = L.species_only;
+    A.queue = L.queue;
+    A.queue_len = L.queue_len;
+    A.queue_head = L.queue_head;
+    if (L.grid == 0) return hipSuccess;
+    kern<<<L.grid, L.block, C::lds, st>>>(A);
+    return hipGetLastError();
+}
+
+template <typename real, int M>
+static hipError_t gpd_tile(const GpdLaunch &L, hipStream_t st) {
+    const int *T = L.tile;
+    if (L.halo != 1) return hipErrorInvalidValue;
+    if (T[0] == 8 && T[1] == 8 && T[2] == 8) return gpd_one<real, M, 8, 8, 8, 1>(L, st);
+    if (T[0] == 8 && T[1] == 8 && T[2] == 4) return gpd_one<real, M, 8, 8, 4, 1>(L, st);
+    if (T[0] == 8 && T[1] == 4 && T[2] == 4) return gpd_one<real, M, 8, 4, 4, 1>(L, st);
+    if (T[0] == 4 && T[1] == 4 && T[2] == 4) return gpd_one<real, M, 4, 4, 4, 1>(L, st);
+    return hipErrorInvalidValue;
+}
+
+bool gpd_supported(const int tile[3], int halo) {
+    if (halo != 1) return false;
+    return (tile[0] == 8 && tile[1] == 8 && (tile[2] == 8 || tile[2] == 4)) ||
+           (tile[0] == 8 && tile[1] == 4 && tile[2] == 4) || (tile[0] == 4 && tile[1] == 4 && tile[2] == 4);
+}
+
+size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo) {
+    int rl_eb = order == 2 ? 2 : 1, rh_eb = 1, rl_j = order == 2 ? 2 : 1, rh_j = 2;
+    size_t neb = 1, nj = 1;
+    for (int d = 0; d < 3; ++d) {
+        neb *= (size_t)(tile[d] + 2 * halo + rl_eb + rh_eb);
+        nj *= (size_t)(tile[d] + 2 * halo + rl_j + rh_j);
+    }
+    return (6 * neb + 3 * nj) * (size_t)prec;
+}
+
+hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st) {
+    if (prec == 8) return order == 2 ? gpd_tile<double, 2>(L, st) : gpd_tile<double, 1>(L, st);
+    return order == 2 ? gpd_tile<float, 2>(L, st) : gpd_tile<float, 1>(L, st);
+}
+
+hipError_t launch_yee(int prec, void *const F[9], void *const Jnext[3], const int n[3], double dt, hipStream_t st) {
+    dim3 blk(64), grd((n[0] + 63) / 64, n[1], n[2]);
+    if (prec == 8) {
+        double *const *f = (double *const *)F;
+        double *const *z = (double *const *)Jnext;
+        k_yee_b<double><<<grd, blk, 0, st>>>(f[3], f[4], f[5], f[0], f[1], f[2], n[0], n[1], n[2], 0.5 * dt);
+        k_yee_e<double><<<grd, blk, 0, st>>>(f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], z[0], z[1], z[2], n[0],
+                                             n[1], n[2], dt);
+        k_yee_b<double><<<grd, blk, 0, st>>>(f[3], f[4], f[5], f[0], f[1], f[2], n[0], n[1], n[2], 0.5 * dt);
+    } else {
+        float *const *f = (float *const *)F;
+        float *const *z = (float *const *)Jnext;
+        float fdt = (float)dt, hdt = (float)(0.5 * dt);
+        k_yee_b<float><<<grd, blk, 0, st>>>(f[3], f[4], f[5], f[0], f[1], f[2], n[0], n[1], n[2], hdt);
+        k_yee_e<float><<<grd, blk, 0, st>>>(f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], z[0], z[1], z[2], n[0],
+                                            n[1], n[2], fdt);
+        k_yee_b<float><<<grd, blk, 0, st>>>(f[3], f[4], f[5], f[0], f[1], f[2], n[0], n[1], n[2], hdt);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,
+                             hipStream_t st) {
+    if (np <= 0) return hipSuccess;
+    if (prec == 8) k_box_counts<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(P), np, G, counts);
+    else k_box_counts<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(P), np, G, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(int prec, const ParticlesRaw &P, int np, const Geom &G, int nb, const int *box_hi,
+                           const FeatScratch &S, float *feat, hipStream_t st) {
+    if (np > 0) {
+        if (prec == 8)
+            k_feat_particles<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(P), np, G, box_hi, S.cellcount, S.spcnt,
+                                                                    S.edge, S.usum);
+        else
+            k_feat_particles<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(P), np, G, box_hi, S.cellcount, S.spcnt,
+                                                                   S.edge, S.usum);
+    }
+    k_feat_boxes<<<nb, 256, 0, st>>>(S.cellcount, G, box_hi, S.spcnt, S.edge, S.usum, feat);
+    return hipGetLastError();
+}
+
+}  // namespace pb

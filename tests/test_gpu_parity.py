@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path against the FP64 oracle on identical seeded inputs.
+
+Tolerances (written here, derived in the design doc):
+  FP64 library vs FP64 oracle: 1e-12, relative to the largest value of each
+  quantity (positions per particle relative to max(1, |x|)).
+  FP32 library vs FP64 oracle after 10 steps: 1e-5 the same way.
+Every case spans several tiles and boxes; particle orders are matched by id.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import picsynth
+from tests._util import (gpu_particles, make_ctx, min_image, normwise, oracle_steps, order_by_species_id,
+                         set_state)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {8: 1e-12, 4: 1e-5}
+
+
+def _pb():
+    from paper_2104_11385_amd import picbal as pb
+    return pb
+
+
+def compare(ctx, wl, x, u, w, sp, ids, F, nsteps, tol, check_fields=True):
+    gx, gu, gids, gsp = gpu_particles(ctx, wl)
+    ox, ou, OF = oracle_steps(wl, x, u, w, sp, F, nsteps)
+    ox, ou, oids, osp = order_by_species_id(ox, ou, ids, sp)
+    np.testing.assert_array_equal(gids, oids)
+    np.testing.assert_array_equal(gsp, osp)
+    dx = np.abs(min_image(gx - ox, wl.n))
+    assert (dx <= tol * np.maximum(1.0, np.abs(ox))).all(), f"max |dx| = {dx.max():.3e}"
+    for s in range(len(wl.species)):
+        m = gsp == s
+        if m.sum() == 0:
+            continue
+        err = normwise(gu[m], ou[m])
+        assert err <= tol, f"species {s}: u error {err:.3e}"
+    if check_fields:
+        GF = ctx.get_fields()
+        for c in range(9):
+            if np.abs(OF[c]).max() == 0:
+                assert np.abs(GF[c]).max() <= 1e-30
+                continue
+            err = normwise(GF[c], OF[c])
+            assert err <= tol, f"field component {c}: error {err:.3e}"
+    return gx, ox
+
+
+def quad_workload(precision=8, n=(16, 16, 24), u_th=0.05, seed=21):
+    return picsynth.small_workload(n=n, box=8, order=2, ppc=2, seed=seed, species=("electrons", "protons"),
+                                   u_th=u_th, precision=precision, region_lo=(0, 0, 4), region_hi=(n[0], n[1], 20))
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_c1_ten_steps(precision):
+    # 32^3, 8 boxes of 16^3, 65,536 electrons, B_z = 1, linear shapes, 10 steps
+    wl = picsynth.config("c1")
+    print(f"[parity] c1 precision={precision}", flush=True)
+    ctx = make_ctx(wl, precision=precision, load=False)
+    x, u, w, ids, sp, F = set_state(ctx, wl)
+    ctx.step(wl.steps)
+    compare(ctx, wl, x, u, w, sp, ids, F, wl.steps, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+@pytest.mark.parametrize("order", [1, 2])
+def test_random_fields_two_species(precision, order):
+    wl = quad_workload(precision)
+    wl.order = order
+    print(f"[parity] two species order={order} precision={precision}", flush=True)
+    ctx = make_ctx(wl, load=False)
+    F0 = picsynth.random_fields(wl.n, 9, amp=0.05)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+    ctx.step(10)
+    compare(ctx, wl, x, u, w, sp, ids, F, 10, TOL[precision])
+
+
+@pytest.mark.parametrize("mode,graph", [(0, False), (1, False), (2, False), (2, True), (0, True)])
+def test_launch_modes_agree_with_oracle(mode, graph):
+    wl = quad_workload(8, seed=5)
+    print(f"[parity] launch mode={mode} graph={graph}", flush=True)
+    ctx = make_ctx(wl, load=False)
+    ctx.set_launch_mode(mode, graph)
+    F0 = picsynth.random_fields(wl.n, 4, amp=0.03)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+    ctx.step(7)
+    compare(ctx, wl, x, u, w, sp, ids, F, 7, TOL[8])
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_fast_particles_take_global_path(precision):
+    # u_th = 0.6: particles drift several cells between sorts, beyond the
+    # staged halo, and must still match through the global-memory path.
+    wl = quad_workload(precision, u_th=0.6, seed=8)
+    print(f"[parity] fast particles precision={precision}", flush=True)
+    ctx = make_ctx(wl, load=False)
+    ctx.set_tuning(sort_interval=1000)
+    F0 = picsynth.random_fields(wl.n, 2, amp=0.02)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+    ctx.slow_path_count()
+    ctx.step(10)
+    assert ctx.slow_path_count() > 0
+    compare(ctx, wl, x, u, w, sp, ids, F, 10, TOL[precision])
+
+
+def test_sort_interval_and_tiles_do_not_change_results():
+    wl = quad_workload(8, seed=12)
+    res = []
+    for tile, si in (((8, 8, 4), 1), ((4, 4, 4), 3), ((8, 4, 4), 50), ((8, 8, 4), 7)):
+        print(f"[parity] tile={tile} sort_interval={si}", flush=True)
+        ctx = make_ctx(wl, load=False)
+        ctx.set_tuning(tile=tile, sort_interval=si)
+        F0 = picsynth.random_fields(wl.n, 6, amp=0.03)
+        x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+        ctx.step(6)
+        gx, _ = compare(ctx, wl, x, u, w, sp, ids, F, 6, TOL[8], check_fields=False)
+        res.append(gx)
+    for r in res[1:]:
+        assert np.abs(min_image(r - res[0], wl.n)).max() < 1e-12
+    # an 8x8x8 tile of double-precision quadratic windows needs more LDS than a CU has
+    ctx = make_ctx(wl, load=False)
+    pb = _pb()
+    with pytest.raises(pb.PicError) as e:
+        ctx.set_tuning(tile=(8, 8, 8))
+    assert e.value.code == pb.PIC_EUNSUPPORTED
+
+
+def test_wrap_edges_and_empty_species():
+    # particles sitting on the periodic faces, moving out of the domain; a
+    # second species with no particles at all
+    wl = picsynth.small_workload(n=(16, 16, 16), box=8, order=2, ppc=1, seed=3,
+                                 species=("electrons", "protons"), precision=8)
+    ctx = make_ctx(wl, load=False)
+    n = 16.0
+    x = np.array([[0.0, 0.0, 0.0], [n - 1e-13, 5.5, 7.25], [3.5, n - 1e-12, 0.0], [15.999, 15.999, 15.999]])
+    u = np.array([[-0.3, -0.2, -0.1], [0.2, 0.0, 0.0], [0.0, 0.4, -0.3], [0.5, 0.5, 0.5]])
+    w = np.full(4, 0.1)
+    ids = np.arange(4)
+    ctx.set_particles(0, x, u, w, ids)
+    ctx.set_particles(1, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0, np.int64))
+    F = picsynth.initial_fields(wl)
+    ctx.set_fields(F)
+    ctx.step(5)
+    sp = np.zeros(4, np.int32)
+    compare(ctx, wl, x, u, w, sp, ids, F, 5, TOL[8])
+    gx, _, _, _ = gpu_particles(ctx, wl)
+    assert ((gx >= 0) & (gx < n)).all()
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_box_counts_after_steps(precision):
+    wl = quad_workload(precision, u_th=0.2, seed=17)
+    ctx = make_ctx(wl, load=False)
+    x, u, w, ids, sp, F = set_state(ctx, wl)
+    ctx.step(10)
+    got = ctx.box_counts()
+    ox, ou, _ = oracle_steps(wl, x, u, w, sp, F, 10)
+    want = oracle.box_counts(wl.boxes, ox, sp, len(wl.species))
+    if precision == 8:
+        np.testing.assert_array_equal(got, want)
+    else:
+        # a count may differ only for particles the oracle places within 1e-5
+        # of a box face
+        frac = ox - np.floor(ox)
+        near = ((frac < 1e-5) | (frac > 1 - 1e-5)).any(axis=1)
+        assert np.abs(got - want).sum() <= 2 * near.sum()
+    assert got.sum() == len(x)
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+def test_device_loader_matches_generator(precision):
+    # pic_init's on-device Philox loader against the host generator
+    wl = quad_workload(precision, seed=77)
+    ctx = make_ctx(wl, load=True)
+    for s in range(2):
+        gx, gu, gw, gi = ctx.get_particles(s)
+        o = np.argsort(gi)
+        gx, gu, gw, gi = gx[o], gu[o], gw[o], gi[o]
+        hx, hu, hw, hi = picsynth.particles(wl, s)
+        np.testing.assert_array_equal(gi, hi)
+        np.testing.assert_array_equal(gx, hx)          # 24-bit offsets: exact in both precisions
+        tol = 1e-14 if precision == 8 else 1e-7
+        assert np.abs(gu - hu).max() <= tol * max(1e-300, np.abs(hu).max()) + (0 if s == 0 else 1e-30)
+        np.testing.assert_allclose(gw, hw, rtol=1e-7 if precision == 4 else 0)
