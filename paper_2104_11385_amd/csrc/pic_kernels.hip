@@ -382,7 +382,9 @@ struct Cfg {
     static constexpr int JZ = TZ + 2 * H + RL_J + RH_J;
     static constexpr int NEB = EX * EY * EZ;
     static constexpr int NJ = JX * JY * JZ;
-    static constexpr size_t lds = (size_t)(6 * NEB + 3 * NJ) * sizeof(real);
+    // J is accumulated in double: gfx950's LDS atomic add is fast for f64
+    // (and integers) but an order of magnitude slower for f32.
+    static constexpr size_t lds = (size_t)(6 * NEB) * sizeof(real) + (size_t)(3 * NJ) * sizeof(double);
 };
 
 // Shape factors of one dimension.  Inputs: d = offset from the reference
@@ -425,6 +427,7 @@ template <typename real, int M>
 struct DepW {
     real S0[M + 2], dS[M + 2];
     int s;
+    bool moved;  // the particle left its reference cell / node this step
     __device__ __forceinline__ void set(real d0, real D) {
         real d1 = d0 + D;
         if (M == 1) {
@@ -448,6 +451,7 @@ struct DepW {
                 dS[2] = (real)0;
             }
             s = km ? -1 : 0;
+            moved = k != 0;
         } else {
             const real h = (real)0.5;
             int k = (d1 >= h) - (d1 < -h);
@@ -474,6 +478,7 @@ struct DepW {
                 dS[3] = (real)0;
             }
             s = km ? -2 : -1;
+            moved = k != 0;
         }
     }
 };
@@ -512,10 +517,12 @@ __device__ __forceinline__ void gather6(const Acc &F, const GatherW<real, M> W[3
 }
 
 // Deposits the Esirkepov current through an accessor J.add(comp, a, b, c, v)
-// with (a,b,c) offsets inside the window.
-template <typename real, int M, typename Acc>
+// with (a,b,c) offsets inside the window.  L = M + 2 is the general window;
+// a particle that keeps its reference node in every dimension has all its
+// weight on the first M + 1 nodes and uses L = M + 1 (the last running sum
+// along each axis is then zero by construction and is not deposited).
+template <typename real, int M, int L, typename Acc>
 __device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real coef) {
-    constexpr int L = M + 2;
     const real h = (real)0.5, third = (real)(1.0 / 3.0);
     J.begin(W[0].s, W[1].s, W[2].s);
     // Jx: running sum along x
@@ -578,14 +585,14 @@ struct LdsEB {
 
 template <typename real, typename C>
 struct LdsJ {
-    real *s;
+    double *s;
     int ref;
     int base;
     __device__ __forceinline__ void begin(int sx, int sy, int sz) {
         base = ref + sx + C::JX * (sy + C::JY * sz);
     }
     __device__ __forceinline__ void add(int comp, int a, int b, int c, real v) {
-        atomic_add_lds(&s[comp * C::NJ + base + a + C::JX * (b + C::JY * c)], v);
+        atomic_add_lds(&s[comp * C::NJ + base + a + C::JX * (b + C::JY * c)], (double)v);
     }
 };
 
@@ -628,7 +635,7 @@ struct GlobJ {
 
 template <typename real, int M, int TX, int TY, int TZ, int H>
 __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, const TileDesc &td, real hq,
-                                              real cq, const real *sEB, real *sJ, unsigned &nslow) {
+                                              real cq, const real *sEB, double *sJ, unsigned &nslow) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
     int c[3];
     unpack_cell(A.P.cell[p], c[0], c[1], c[2]);
@@ -703,9 +710,11 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
 #pragma unroll
     for (int d = 0; d < 3; ++d) DW[d].set(d0[d], D[d]);
     real coef = cq * w;
+    bool moved = DW[0].moved || DW[1].moved || DW[2].moved;
     if (fast) {
         LdsJ<real, C> acc{sJ, (rel[0] + H + C::RL_J) + C::JX * ((rel[1] + H + C::RL_J) + C::JY * (rel[2] + H + C::RL_J)), 0};
-        deposit3<real, M>(acc, DW, coef);
+        if (moved) deposit3<real, M, M + 2>(acc, DW, coef);
+        else deposit3<real, M, M + 1>(acc, DW, coef);
     } else {
         GlobJ<real> acc;
         acc.J = A.J;
@@ -714,7 +723,7 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
             acc.n[d] = A.n[d];
             acc.r[d] = ref[d];
         }
-        deposit3<real, M>(acc, DW, coef);
+        deposit3<real, M, M + 2>(acc, DW, coef);
     }
 
     // new canonical position: cell + offset in [0, 1), periodic wrap
@@ -752,7 +761,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *sEB = reinterpret_cast<real *>(smem_raw);
-    real *sJ = sEB + 6 * C::NEB;
+    double *sJ = reinterpret_cast<double *>(smem_raw + (size_t)6 * C::NEB * sizeof(real));
     __shared__ unsigned long long sCyc, sRtc;
     __shared__ unsigned int sSlow;
     __shared__ int sItem[3];
@@ -805,7 +814,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             int gz = wrap_any(td.z0 - H - C::RL_EB + lz, A.n[2]);
             sEB[i] = A.EB[comp][gx + (size_t)A.n[0] * (gy + (size_t)A.n[1] * gz)];
         }
-        for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = (real)0;
+        for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = 0.0;
         if (tid == 0) {
             sCyc = 0;
             sRtc = 0;
@@ -833,7 +842,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
 
         // flush the J window
         for (int i = tid; i < 3 * C::NJ; i += nthr) {
-            real v = sJ[i];
+            real v = (real)sJ[i];
             if (v != (real)0) {
                 int comp = i / C::NJ;
                 int r = i - comp * C::NJ;
@@ -1133,7 +1142,7 @@ size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo) {
         neb *= (size_t)(tile[d] + 2 * halo + rl_eb + rh_eb);
         nj *= (size_t)(tile[d] + 2 * halo + rl_j + rh_j);
     }
-    return (6 * neb + 3 * nj) * (size_t)prec;
+    return 6 * neb * (size_t)prec + 3 * nj * sizeof(double);
 }
 
 hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st) {

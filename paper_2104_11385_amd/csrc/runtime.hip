@@ -518,7 +518,7 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     c->tun.chunk = 4096;
     c->tun.sort_interval = 20;
     c->tun.blocks_per_cu = 2;
-    const int cand[4][3] = {{8, 8, 4}, {8, 4, 4}, {4, 4, 4}, {8, 8, 8}};
+    const int cand[4][3] = {{8, 4, 4}, {4, 4, 4}, {8, 8, 4}, {8, 8, 8}};
     bool chosen = false;
     for (auto &t : cand) {
         bool ok = true;
@@ -526,7 +526,7 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
             for (int d = 0; d < 3; ++d)
                 if ((boxes[b].hi[d] - boxes[b].lo[d]) % t[d]) ok = false;
         if (!ok) continue;
-        if (gpd_lds_bytes(c->prec, c->order, t, 1) > 64 * 1024) continue;
+        if (gpd_lds_bytes(c->prec, c->order, t, 1) > 80 * 1024) continue;  // two blocks per CU
         std::memcpy(c->tun.tile, t, sizeof(int) * 3);
         chosen = true;
         break;
