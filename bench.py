@@ -201,6 +201,68 @@ def cpu_baseline(sample_particles=3_000_000):
                       f"scaled to {n_p} particles"}
 
 
+def ctx_for(wl, stream=None):
+    """Library context for any synthetic workload (particles generated on the device)."""
+    from paper_2104_11385_amd import picbal as pb
+    sp = []
+    for s in wl.species:
+        if s.box_ppc is not None:
+            sp.append(pb.Species(s.charge, s.mass, s.density, load_mode=2, box_ppc=s.box_ppc, u_th=s.u_th,
+                                 u_drift=s.u_drift))
+        else:
+            sp.append(pb.Species(s.charge, s.mass, s.density, load_mode=1, ppc=s.ppc, region_lo=s.region_lo,
+                                 region_hi=s.region_hi if s.region_hi is not None else wl.n, u_th=s.u_th,
+                                 u_drift=s.u_drift))
+    prec = pb.PIC_FP64 if wl.precision == 8 else pb.PIC_FP32
+    return pb.pic_init(wl.n, wl.boxes, sp, wl.dt, wl.order, prec, wl.seed, b_ext=wl.b_ext, stream=stream)
+
+
+def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, name="c4"):
+    """Balancing study on the 384x384x768 / 3456-box drifting-slab workload:
+    trains the learned model on two runs (seeds 4 and 6, 207,360 samples),
+    then scores heuristic, device-timer and learned costs with SFC and
+    knapsack over 96 virtual ranks on a held-out run (seed 5)."""
+    import picsynth
+    from paper_2104_11385_amd import lb_study as S
+    from paper_2104_11385_amd import picbal as pb
+    t_start = time.perf_counter()
+    recs = []
+    for seed in train_seeds:
+        wl = picsynth.config(name) if isinstance(name, str) else name()
+        wl.seed = seed
+        ctx = ctx_for(wl)
+        recs.append(S.collect(ctx, steps, interval))
+        ctx.finalize()
+    X, y = S.training_set(recs)
+    wl = picsynth.config(name) if isinstance(name, str) else name()
+    wl.seed = eval_seed
+    ctx = ctx_for(wl)
+    t0 = time.perf_counter()
+    loss = ctx.mlp_train(X, y, epochs=30, batch=1024, seed=eval_seed)
+    train_s = time.perf_counter() - t0
+    rec = S.collect(ctx, steps, interval, learned=True)
+    # inference cost on 4096 boxes of features (the mixed-box layout's count)
+    Xi = np.ascontiguousarray(np.resize(rec["feat"].reshape(-1, 16), (4096, 16)))
+    ctx.mlp_predict(Xi)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        ctx.mlp_predict(Xi)
+    infer_us = (time.perf_counter() - t0) / 20 * 1e6
+    E = S.evaluate(rec, wl.boxes, ranks)
+    summ = S.summary(E)
+    fallbacks = int(sum(1 for u in rec["learned_used"] if u != pb.PIC_COST_LEARNED))
+    ctx.finalize()
+    out = {"E_mean": summ, "rebalances": int(len(rec["timer"]) - 1),
+           "learned_over_timer": {p: summ["learned"][p] / summ["timer"][p] for p in summ["timer"]},
+           "learned_minus_heuristic": {p: summ["learned"][p] - summ["heuristic"][p] for p in summ["timer"]},
+           "learned_fallbacks": fallbacks, "train_samples": int(len(y)), "train_loss_first_last":
+           [float(loss[0]), float(loss[-1])], "train_seconds": train_s, "mlp_predict_4096_us": infer_us,
+           "ranks": ranks, "interval": interval, "steps": steps, "wall_s": time.perf_counter() - t_start,
+           "workload": "384x384x768, 3456 boxes of 32^3, e-/p+ slab z in [374,394) at 16 ppc each drifting "
+                       "u_z=0.05, quadratic, FP32; train seeds 4,6; evaluate seed 5"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +274,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the other launch modes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-lb", action="store_true", help="skip the load-balancing study")
+    ap.add_argument("--lb-steps", type=int, default=300)
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -250,6 +314,8 @@ def main():
         "yee_ms": r["yee_ms"], "slow_path_particles": r["slow_path"],
         "timer_cost_spearman_vs_count": r["timer_cost_spearman_vs_count"],
     }
+    if not args.no_lb:
+        out["lb_study"] = lb_study(steps=args.lb_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

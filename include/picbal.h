@@ -168,10 +168,14 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
 
 /* costs[n_boxes] (caller-owned) receives the per-box cost of `strategy`.
  * Device-timer strategies return the counters accumulated since the last
- * pic_reset_costs (or pic_init).  LEARNED falls back to HEURISTIC when no
- * model is loaded or when the model's mean relative error against the last
- * measured timer costs exceeds 15%; *used_strategy (nullable) reports which
- * strategy produced the values. */
+ * pic_reset_costs (or pic_init).  LEARNED predicts the next interval's
+ * timer cycles from the current box features; it falls back to HEURISTIC
+ * when no model is loaded, or when the prediction made at the previous
+ * LEARNED call missed the timer costs read since then (the interval it was
+ * made for) by more than 15% mean relative error over boxes with nonzero
+ * cycles.  Intended order per balancing step: read DEVICE_TIMER, reset,
+ * then LEARNED.  *used_strategy (nullable) reports which strategy produced
+ * the values. */
 PIC_API int pic_box_costs(pic_ctx *ctx, int32_t strategy, double *costs, int32_t *used_strategy);
 
 /* Zeroes the device-timer counters. */
@@ -245,7 +249,9 @@ PIC_API int32_t pic_mlp_nparam(void);
 /* Trains the 16-64-64-1 ReLU network (bf16 matrix-core operands, fp32
  * accumulation and master weights) on the device to predict y from X
  * (X[n][16] raw features, standardised internally with their mean and std;
- * y[n] = ln cycles), minimising the mean squared error with Adam
+ * y[n] = ln(1 + device-timer cycles), so that boxes without work are
+ * represented; PIC_COST_LEARNED then reports max(0, exp(yhat) - 1)),
+ * minimising the mean squared error with Adam
  * (lr 1e-3, betas 0.9/0.999, eps 1e-8), minibatch `batch`, `epochs` passes.
  * perm[epochs][n] (nullable) gives each epoch's sample order; NULL uses a
  * seeded shuffle.  init_w[nparam] (nullable) sets the initial weights, else

@@ -10,6 +10,7 @@
 namespace pb {
 
 constexpr int kMaxSpecies = 4;
+constexpr int kSubQueues = 8;   // one persistent work sub-queue per XCD
 
 // Particle cell index packed in 32 bits: x in bits 0..10, y in 11..21,
 // z in 22..31 (domain up to 2048 x 2048 x 1024 cells).
@@ -79,8 +80,8 @@ struct GpdArgs {
     int tile_base;             // PER_BOX: first tile of the box
     int species_only;          // PER_BOX: species of this launch
     const int4 *queue;         // PERSISTENT: (tile, begin, end, -)
-    const int *queue_len;
-    int *queue_head;
+    const int *queue_bounds;   // [kSubQueues + 1] sub-queue ranges
+    int *queue_head;           // [kSubQueues] next item of each sub-queue
 };
 
 }  // namespace pb

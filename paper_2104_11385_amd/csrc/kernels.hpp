@@ -47,10 +47,10 @@ struct SortScratch {
 
 struct QueueScratch {
     int ncls;
-    int *cls_cnt;             // [ncls]
-    int *cursor;              // [ncls]
-    int *queue_len;           // [1]
-    int *queue_head;          // [1]
+    int *cls_cnt;             // [kSubQueues * ncls]
+    int *cursor;              // [kSubQueues * ncls]
+    int *queue_bounds;        // [kSubQueues + 1]
+    int *queue_head;          // [kSubQueues]
     int4 *queue;              // [max items]
 };
 
@@ -79,7 +79,7 @@ struct GpdLaunch {
     int tile_base;
     int species_only;
     const int4 *queue;
-    const int *queue_len;
+    const int *queue_bounds;
     int *queue_head;
     int tile[3];
     int halo;
@@ -91,6 +91,7 @@ hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, i
                        const SortScratch &W, hipStream_t st);
 hipError_t launch_queue(const int *segstart, int ntiles, int nsp, int chunk, const QueueScratch &Q, hipStream_t st);
 hipError_t launch_set_int(int *p, int v, hipStream_t st);
+hipError_t launch_reset_heads(int *heads, hipStream_t st);
 hipError_t launch_fill_f(int prec, void *a, double v, size_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *a, size_t n, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st);
@@ -98,7 +99,13 @@ hipError_t launch_fill_f64(double *a, size_t n, hipStream_t st);
 hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st);
 bool gpd_supported(const int tile[3], int halo);
 size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo);
-hipError_t launch_yee(int prec, void *const F[9], void *const Jnext[3], const int n[3], double dt, hipStream_t st);
+// Field buffers of one Yee update: inputs E, B, J; outputs Eo, Bo; Z is the
+// J buffer cleared for the next deposit.
+struct YeeBuffers {
+    const void *E[3], *B[3], *J[3];
+    void *Eo[3], *Bo[3], *Z[3];
+};
+hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
 hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,
                              hipStream_t st);
 hipError_t launch_features(int prec, const ParticlesRaw &P, int np, const Geom &G, int nb, const int *box_hi,

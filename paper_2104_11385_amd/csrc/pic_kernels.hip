@@ -313,25 +313,39 @@ __device__ __forceinline__ int size_class(int sz, int chunk, int ncls) {
     return c < 0 ? 0 : (c >= ncls ? ncls - 1 : c);
 }
 
+// Sub-queue of tile t: contiguous tile ranges holding equal shares of the
+// particles, one per XCD, so that neighbouring tiles share an L2.
+__device__ __forceinline__ int sub_queue(const int *segstart, int t, int ntiles, int nsp) {
+    long long tot = segstart[ntiles * nsp];
+    if (tot <= 0) return 0;
+    int x = (int)(((long long)segstart[t * nsp] * kSubQueues) / tot);
+    return x < kSubQueues ? x : kSubQueues - 1;
+}
+
 __global__ void k_queue_count(const int *segstart, int ntiles, int nsp, int chunk, int ncls, int *cls_cnt) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     int n = segstart[(t + 1) * nsp] - segstart[t * nsp];
     if (n == 0) return;
+    int x = sub_queue(segstart, t, ntiles, nsp);
     int full = n / chunk, rem = n - full * chunk;
-    if (full) atomicAdd(&cls_cnt[0], full);
-    if (rem) atomicAdd(&cls_cnt[size_class(rem, chunk, ncls)], 1);
+    if (full) atomicAdd(&cls_cnt[x * ncls], full);
+    if (rem) atomicAdd(&cls_cnt[x * ncls + size_class(rem, chunk, ncls)], 1);
 }
 
-__global__ void k_queue_scan(int *cls_cnt, int *cursor, int ncls, int *queue_len) {
+// Bucket offsets: sub-queue major, size class (largest first) minor.
+__global__ void k_queue_scan(int *cls_cnt, int *cursor, int ncls, int *qbounds) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int acc = 0;
-    for (int c = 0; c < ncls; ++c) {
-        cursor[c] = acc;
-        acc += cls_cnt[c];
-        cls_cnt[c] = 0;
+    for (int x = 0; x < kSubQueues; ++x) {
+        qbounds[x] = acc;
+        for (int c = 0; c < ncls; ++c) {
+            cursor[x * ncls + c] = acc;
+            acc += cls_cnt[x * ncls + c];
+            cls_cnt[x * ncls + c] = 0;
+        }
     }
-    *queue_len = acc;
+    qbounds[kSubQueues] = acc;
 }
 
 __global__ void k_queue_fill(const int *segstart, int ntiles, int nsp, int chunk, int ncls, int *cursor,
@@ -340,15 +354,20 @@ __global__ void k_queue_fill(const int *segstart, int ntiles, int nsp, int chunk
     if (t >= ntiles) return;
     int b = segstart[t * nsp], n = segstart[(t + 1) * nsp] - b;
     if (n == 0) return;
+    int x = sub_queue(segstart, t, ntiles, nsp);
     int full = n / chunk, rem = n - full * chunk;
     if (full) {
-        int pos = atomicAdd(&cursor[0], full);
+        int pos = atomicAdd(&cursor[x * ncls], full);
         for (int j = 0; j < full; ++j) queue[pos + j] = make_int4(t, b + j * chunk, b + (j + 1) * chunk, 0);
     }
     if (rem) {
-        int pos = atomicAdd(&cursor[size_class(rem, chunk, ncls)], 1);
+        int pos = atomicAdd(&cursor[x * ncls + size_class(rem, chunk, ncls)], 1);
         queue[pos] = make_int4(t, b + full * chunk, b + n, 0);
     }
+}
+
+__global__ void k_reset_heads(int *heads) {
+    if (threadIdx.x < kSubQueues && blockIdx.x == 0) heads[threadIdx.x] = 0;
 }
 
 __global__ void k_set_int(int *p, int v) {
@@ -525,18 +544,18 @@ template <typename real, int M, int L, typename Acc>
 __device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real coef) {
     const real h = (real)0.5, third = (real)(1.0 / 3.0);
     J.begin(W[0].s, W[1].s, W[2].s);
-    // Jx: running sum along x
+    // Jx: running sum along x (coef folded into the transverse factor)
 #pragma unroll
     for (int c = 0; c < L; ++c)
 #pragma unroll
         for (int b = 0; b < L; ++b) {
-            real in = W[1].S0[b] * W[2].S0[c] + h * (W[1].dS[b] * W[2].S0[c] + W[1].S0[b] * W[2].dS[c]) +
-                      third * W[1].dS[b] * W[2].dS[c];
+            real in = coef * (W[1].S0[b] * W[2].S0[c] + h * (W[1].dS[b] * W[2].S0[c] + W[1].S0[b] * W[2].dS[c]) +
+                              third * W[1].dS[b] * W[2].dS[c]);
             real acc = (real)0;
 #pragma unroll
             for (int a = 0; a < L - 1; ++a) {
                 acc += W[0].dS[a] * in;
-                J.add(0, a, b, c, coef * acc);
+                J.add(0, a, b, c, acc);
             }
         }
     // Jy: running sum along y
@@ -544,13 +563,13 @@ __device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real 
     for (int c = 0; c < L; ++c)
 #pragma unroll
         for (int a = 0; a < L; ++a) {
-            real in = W[0].S0[a] * W[2].S0[c] + h * (W[0].dS[a] * W[2].S0[c] + W[0].S0[a] * W[2].dS[c]) +
-                      third * W[0].dS[a] * W[2].dS[c];
+            real in = coef * (W[0].S0[a] * W[2].S0[c] + h * (W[0].dS[a] * W[2].S0[c] + W[0].S0[a] * W[2].dS[c]) +
+                              third * W[0].dS[a] * W[2].dS[c]);
             real acc = (real)0;
 #pragma unroll
             for (int b = 0; b < L - 1; ++b) {
                 acc += W[1].dS[b] * in;
-                J.add(1, a, b, c, coef * acc);
+                J.add(1, a, b, c, acc);
             }
         }
     // Jz: running sum along z
@@ -558,13 +577,13 @@ __device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real 
     for (int b = 0; b < L; ++b)
 #pragma unroll
         for (int a = 0; a < L; ++a) {
-            real in = W[0].S0[a] * W[1].S0[b] + h * (W[0].dS[a] * W[1].S0[b] + W[0].S0[a] * W[1].dS[b]) +
-                      third * W[0].dS[a] * W[1].dS[b];
+            real in = coef * (W[0].S0[a] * W[1].S0[b] + h * (W[0].dS[a] * W[1].S0[b] + W[0].S0[a] * W[1].dS[b]) +
+                              third * W[0].dS[a] * W[1].dS[b]);
             real acc = (real)0;
 #pragma unroll
             for (int c = 0; c < L - 1; ++c) {
                 acc += W[2].dS[c] * in;
-                J.add(2, a, b, c, coef * acc);
+                J.add(2, a, b, c, acc);
             }
         }
 }
@@ -767,19 +786,27 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     __shared__ int sItem[3];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nsp = A.nsp;
+    const int home = blockIdx.x % kSubQueues;  // blocks are dealt round-robin over the XCDs
+    int sq = 0;                                // sub-queues already found empty (thread 0)
 
     for (int iter = 0;; ++iter) {
         int tile, pbeg, pend;
         if (A.mode == MODE_PERSISTENT) {
+            // own XCD's sub-queue first, then steal from the others
             if (tid == 0) {
-                int q = atomicAdd(A.queue_head, 1);
-                if (q < *A.queue_len) {
-                    int4 it = A.queue[q];
-                    sItem[0] = it.x;
-                    sItem[1] = it.y;
-                    sItem[2] = it.z;
-                } else {
-                    sItem[0] = -1;
+                sItem[0] = -1;
+                for (; sq < kSubQueues; ++sq) {
+                    int x = (home + sq) % kSubQueues;
+                    int lo = A.queue_bounds[x], hi = A.queue_bounds[x + 1];
+                    if (hi <= lo) continue;
+                    int q = atomicAdd(&A.queue_head[x], 1);
+                    if (lo + q < hi) {
+                        int4 it = A.queue[lo + q];
+                        sItem[0] = it.x;
+                        sItem[1] = it.y;
+                        sItem[2] = it.z;
+                        break;
+                    }
                 }
             }
             __syncthreads();
@@ -866,50 +893,164 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
 }
 
 // ---------------------------------------------------------------------------
-// Yee update
+// Yee update, one pass: B^{n+1/2} = B^n - dt/2 curl E^n; E^{n+1} = E^n +
+// dt (curl B^{n+1/2} - J); B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}.
+// A block owns an x-y tile and marches along z with ring buffers of planes in
+// LDS: E^n (two planes), B^{n+1/2} (two), E^{n+1} (two), plus B^n and J of
+// the current plane.  Inputs are read once and outputs written once into the
+// other field buffer; the next step's J buffer is cleared on the way.
+// Plane arrays cover in-plane offsets -1 .. T+1 (index + 1).
 // ---------------------------------------------------------------------------
 
-template <typename real>
-__global__ void k_yee_b(real *Bx, real *By, real *Bz, const real *Ex, const real *Ey, const real *Ez, int nx,
-                        int ny, int nz, real hdt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y, k = blockIdx.z;
-    if (i >= nx) return;
-    int ip = i + 1 == nx ? 0 : i + 1, jp = j + 1 == ny ? 0 : j + 1, kp = k + 1 == nz ? 0 : k + 1;
-    size_t sy = nx, sz = (size_t)nx * ny;
-    size_t c = i + sy * j + sz * k;
-    size_t cxp = ip + sy * j + sz * k, cyp = i + sy * jp + sz * k, czp = i + sy * j + sz * kp;
-    real ex = Ex[c], ey = Ey[c], ez = Ez[c];
-    real cx = (Ez[cyp] - ez) - (Ey[czp] - ey);
-    real cy = (Ex[czp] - ex) - (Ez[cxp] - ez);
-    real cz = (Ey[cxp] - ey) - (Ex[cyp] - ex);
-    Bx[c] -= hdt * cx;
-    By[c] -= hdt * cy;
-    Bz[c] -= hdt * cz;
-}
+constexpr int YTX = 32, YTY = 8, YPX = YTX + 3, YPY = YTY + 3, YPN = YPX * YPY;
+
+struct YeeArgs {
+    const void *E[3], *B[3], *J[3];
+    void *Eo[3], *Bo[3], *Z[3];
+    int n[3];
+    int zc;       // planes per block
+    double dt;
+};
 
 template <typename real>
-__global__ void k_yee_e(real *Ex, real *Ey, real *Ez, const real *Bx, const real *By, const real *Bz,
-                        const real *Jx, const real *Jy, const real *Jz, real *Zx, real *Zy, real *Zz, int nx,
-                        int ny, int nz, real dt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y, k = blockIdx.z;
-    if (i >= nx) return;
-    int im = i == 0 ? nx - 1 : i - 1, jm = j == 0 ? ny - 1 : j - 1, km = k == 0 ? nz - 1 : k - 1;
-    size_t sy = nx, sz = (size_t)nx * ny;
-    size_t c = i + sy * j + sz * k;
-    size_t cxm = im + sy * j + sz * k, cym = i + sy * jm + sz * k, czm = i + sy * j + sz * km;
-    real bx = Bx[c], by = By[c], bz = Bz[c];
-    real cx = (bz - Bz[cym]) - (by - By[czm]);
-    real cy = (bx - Bx[czm]) - (bz - Bz[cxm]);
-    real cz = (by - By[cxm]) - (bx - Bx[cym]);
-    Ex[c] += dt * (cx - Jx[c]);
-    Ey[c] += dt * (cy - Jy[c]);
-    Ez[c] += dt * (cz - Jz[c]);
-    // clear the other J buffer for the next step's deposit
-    Zx[c] = (real)0;
-    Zy[c] = (real)0;
-    Zz[c] = (real)0;
+__global__ __launch_bounds__(256) void k_yee_fused(YeeArgs a) {
+    extern __shared__ __align__(16) unsigned char ysm[];
+    real *base = reinterpret_cast<real *>(ysm);
+    // plane buffers, 3 components each
+    real *En[2], *Bh[2], *Ep[2], *Bn, *Jn;
+    En[0] = base;
+    En[1] = En[0] + 3 * YPN;
+    Bh[0] = En[1] + 3 * YPN;
+    Bh[1] = Bh[0] + 3 * YPN;
+    Ep[0] = Bh[1] + 3 * YPN;
+    Ep[1] = Ep[0] + 3 * YPN;
+    Bn = Ep[1] + 3 * YPN;
+    Jn = Bn + 3 * YPN;
+    const real *E0 = (const real *)a.E[0], *E1 = (const real *)a.E[1], *E2 = (const real *)a.E[2];
+    const real *B0 = (const real *)a.B[0], *B1 = (const real *)a.B[1], *B2 = (const real *)a.B[2];
+    const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+    const int x0 = blockIdx.x * YTX, y0 = blockIdx.y * YTY;
+    const int z0 = blockIdx.z * a.zc, z1 = min(nz, z0 + a.zc);
+    const real dt = (real)a.dt, hdt = (real)(0.5 * a.dt);
+    const int tid = threadIdx.x;
+    const size_t sxy = (size_t)nx * ny;
+    auto gidx = [&](int li, int lj, int z) -> size_t {
+        int gx = wrap_any(x0 + li, nx), gy = wrap_any(y0 + lj, ny);
+        return (size_t)gx + (size_t)nx * gy + sxy * (size_t)z;
+    };
+    auto at = [](int li, int lj) { return (li + 1) + YPX * (lj + 1); };
+    // load E^n of plane z over offsets [-1, T+1]
+    auto loadE = [&](real *dst, int z) {
+        for (int q = tid; q < YPN; q += 256) {
+            int li = q % YPX - 1, lj = q / YPX - 1;
+            size_t g = gidx(li, lj, z);
+            dst[q] = E0[g];
+            dst[YPN + q] = E1[g];
+            dst[2 * YPN + q] = E2[g];
+        }
+    };
+    // B^{n+1/2} of plane z over [-1, T] from B^n (Bn) and E^n planes z, z+1
+    auto halfB = [&](real *dst, const real *e, const real *ez) {
+        for (int q = tid; q < YPN; q += 256) {
+            int li = q % YPX - 1, lj = q / YPX - 1;
+            if (li > YTX || lj > YTY) continue;
+            int c = at(li, lj), cx = at(li + 1, lj), cy = at(li, lj + 1);
+            real cxv = (e[2 * YPN + cy] - e[2 * YPN + c]) - (ez[YPN + c] - e[YPN + c]);
+            real cyv = (ez[c] - e[c]) - (e[2 * YPN + cx] - e[2 * YPN + c]);
+            real czv = (e[YPN + cx] - e[YPN + c]) - (e[cy] - e[c]);
+            dst[c] = Bn[c] - hdt * cxv;
+            dst[YPN + c] = Bn[YPN + c] - hdt * cyv;
+            dst[2 * YPN + c] = Bn[2 * YPN + c] - hdt * czv;
+        }
+    };
+    int cur = 0;
+    // prologue: E^n(z0-1), E^n(z0), B^n(z0-1) -> B^{n+1/2}(z0-1)
+    const int zm = wrap_any(z0 - 1, nz);
+    loadE(En[cur], zm);
+    loadE(En[1 - cur], z0);
+    for (int q = tid; q < YPN; q += 256) {
+        int li = q % YPX - 1, lj = q / YPX - 1;
+        if (li > YTX || lj > YTY) continue;
+        size_t g = gidx(li, lj, zm);
+        Bn[q] = B0[g];
+        Bn[YPN + q] = B1[g];
+        Bn[2 * YPN + q] = B2[g];
+    }
+    __syncthreads();
+    int hb = 0;  // Bh[hb] holds plane k-1
+    halfB(Bh[hb], En[cur], En[1 - cur]);
+    cur = 1 - cur;  // En[cur] = E^n(z0)
+    int ep = 0;     // Ep[ep] holds E^{n+1}(k-1)
+    __syncthreads();
+    for (int k = z0; k <= z1; ++k) {
+        const int kz = wrap_any(k, nz), kn = wrap_any(k + 1, nz);
+        // E^n(k+1) into the free E plane; B^n(k) and J(k)
+        loadE(En[1 - cur], kn);
+        for (int q = tid; q < YPN; q += 256) {
+            int li = q % YPX - 1, lj = q / YPX - 1;
+            if (li > YTX || lj > YTY) continue;
+            size_t g = gidx(li, lj, kz);
+            Bn[q] = B0[g];
+            Bn[YPN + q] = B1[g];
+            Bn[2 * YPN + q] = B2[g];
+            if (li >= 0 && lj >= 0) {
+                Jn[q] = ((const real *)a.J[0])[g];
+                Jn[YPN + q] = ((const real *)a.J[1])[g];
+                Jn[2 * YPN + q] = ((const real *)a.J[2])[g];
+            }
+        }
+        __syncthreads();
+        halfB(Bh[1 - hb], En[cur], En[1 - cur]);   // B^{n+1/2}(k)
+        __syncthreads();
+        // E^{n+1}(k) over [0, T]
+        {
+            const real *b = Bh[1 - hb], *bz = Bh[hb], *e = En[cur];
+            real *o = Ep[1 - ep];
+            for (int q = tid; q < YPN; q += 256) {
+                int li = q % YPX - 1, lj = q / YPX - 1;
+                if (li < 0 || lj < 0 || li > YTX || lj > YTY) continue;
+                int c = at(li, lj), cx = at(li - 1, lj), cy = at(li, lj - 1);
+                real cxv = (b[2 * YPN + c] - b[2 * YPN + cy]) - (b[YPN + c] - bz[YPN + c]);
+                real cyv = (b[c] - bz[c]) - (b[2 * YPN + c] - b[2 * YPN + cx]);
+                real czv = (b[YPN + c] - b[YPN + cx]) - (b[c] - b[cy]);
+                o[c] = e[c] + dt * (cxv - Jn[c]);
+                o[YPN + c] = e[YPN + c] + dt * (cyv - Jn[YPN + c]);
+                o[2 * YPN + c] = e[2 * YPN + c] + dt * (czv - Jn[2 * YPN + c]);
+            }
+        }
+        __syncthreads();
+        // write E^{n+1}(k); B^{n+1}(k-1) from B^{n+1/2}(k-1) and E^{n+1}(k-1), E^{n+1}(k)
+        for (int q = tid; q < YTX * YTY; q += 256) {
+            int li = q % YTX, lj = q / YTX;
+            if (x0 + li >= nx || y0 + lj >= ny) continue;
+            int c = at(li, lj);
+            if (k < z1) {
+                size_t g = (size_t)(x0 + li) + (size_t)nx * (y0 + lj) + sxy * (size_t)kz;
+                const real *o = Ep[1 - ep];
+                ((real *)a.Eo[0])[g] = o[c];
+                ((real *)a.Eo[1])[g] = o[YPN + c];
+                ((real *)a.Eo[2])[g] = o[2 * YPN + c];
+                ((real *)a.Z[0])[g] = (real)0;
+                ((real *)a.Z[1])[g] = (real)0;
+                ((real *)a.Z[2])[g] = (real)0;
+            }
+            if (k > z0) {
+                const real *e = Ep[ep], *ez = Ep[1 - ep], *bh = Bh[hb];
+                int cx = at(li + 1, lj), cy = at(li, lj + 1);
+                real cxv = (e[2 * YPN + cy] - e[2 * YPN + c]) - (ez[YPN + c] - e[YPN + c]);
+                real cyv = (ez[c] - e[c]) - (e[2 * YPN + cx] - e[2 * YPN + c]);
+                real czv = (e[YPN + cx] - e[YPN + c]) - (e[cy] - e[c]);
+                size_t g = (size_t)(x0 + li) + (size_t)nx * (y0 + lj) + sxy * (size_t)wrap_any(k - 1, nz);
+                ((real *)a.Bo[0])[g] = bh[c] - hdt * cxv;
+                ((real *)a.Bo[1])[g] = bh[YPN + c] - hdt * cyv;
+                ((real *)a.Bo[2])[g] = bh[2 * YPN + c] - hdt * czv;
+            }
+        }
+        __syncthreads();
+        cur = 1 - cur;
+        hb = 1 - hb;
+        ep = 1 - ep;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1040,13 +1181,18 @@ hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, i
 
 hipError_t launch_queue(const int *segstart, int ntiles, int nsp, int chunk, const QueueScratch &Q, hipStream_t st) {
     k_queue_count<<<nblk(ntiles, 256), 256, 0, st>>>(segstart, ntiles, nsp, chunk, Q.ncls, Q.cls_cnt);
-    k_queue_scan<<<1, 64, 0, st>>>(Q.cls_cnt, Q.cursor, Q.ncls, Q.queue_len);
+    k_queue_scan<<<1, 64, 0, st>>>(Q.cls_cnt, Q.cursor, Q.ncls, Q.queue_bounds);
     k_queue_fill<<<nblk(ntiles, 256), 256, 0, st>>>(segstart, ntiles, nsp, chunk, Q.ncls, Q.cursor, Q.queue);
     return hipGetLastError();
 }
 
 hipError_t launch_set_int(int *p, int v, hipStream_t st) {
     k_set_int<<<1, 64, 0, st>>>(p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_heads(int *heads, hipStream_t st) {
+    k_reset_heads<<<1, 64, 0, st>>>(heads);
     return hipGetLastError();
 }
 
@@ -1111,7 +1257,7 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
     A.tile_base = L.tile_base;
     A.species_only = L.species_only;
     A.queue = L.queue;
-    A.queue_len = L.queue_len;
+    A.queue_bounds = L.queue_bounds;
     A.queue_head = L.queue_head;
     if (L.grid == 0) return hipSuccess;
     kern<<<L.grid, L.block, C::lds, st>>>(A);
@@ -1150,23 +1296,32 @@ hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st) {
     return order == 2 ? gpd_tile<float, 2>(L, st) : gpd_tile<float, 1>(L, st);
 }
 
-hipError_t launch_yee(int prec, void *const F[9], void *const Jnext[3], const int n[3], double dt, hipStream_t st) {
-    dim3 blk(64), grd((n[0] + 63) / 64, n[1], n[2]);
+hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
+    YeeArgs a;
+    for (int c = 0; c < 3; ++c) {
+        a.E[c] = Y.E[c];
+        a.B[c] = Y.B[c];
+        a.J[c] = Y.J[c];
+        a.Eo[c] = Y.Eo[c];
+        a.Bo[c] = Y.Bo[c];
+        a.Z[c] = Y.Z[c];
+        a.n[c] = n[c];
+    }
+    a.dt = dt;
+    a.zc = n[2] >= 256 ? 32 : (n[2] >= 64 ? 16 : 8);
+    dim3 grd((n[0] + YTX - 1) / YTX, (n[1] + YTY - 1) / YTY, (n[2] + a.zc - 1) / a.zc);
+    size_t lds = (size_t)8 * 3 * YPN * prec;
     if (prec == 8) {
-        double *const *f = (double *const *)F;
-        double *const *z = (double *const *)Jnext;
-        k_yee_b<double><<<grd, blk, 0, st>>>(f[3], f[4], f[5], f[0], f[1], f[2], n[0], n[1], n[2], 0.5 * dt);
-        k_yee_e<double><<<grd, blk, 0, st>>>(f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], z[0], z[1], z[2], n[0],
-                                             n[1], n[2], dt);
-        k_yee_b<double><<<grd, blk, 0, st>>>(f[3], f[4], f[5], f[0], f[1], f[2], n[0], n[1], n[2], 0.5 * dt);
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void *)k_yee_fused<double>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        k_yee_fused<double><<<grd, 256, lds, st>>>(a);
     } else {
-        float *const *f = (float *const *)F;
-        float *const *z = (float *const *)Jnext;
-        float fdt = (float)dt, hdt = (float)(0.5 * dt);
-        k_yee_b<float><<<grd, blk, 0, st>>>(f[3], f[4], f[5], f[0], f[1], f[2], n[0], n[1], n[2], hdt);
-        k_yee_e<float><<<grd, blk, 0, st>>>(f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], z[0], z[1], z[2], n[0],
-                                            n[1], n[2], fdt);
-        k_yee_b<float><<<grd, blk, 0, st>>>(f[3], f[4], f[5], f[0], f[1], f[2], n[0], n[1], n[2], hdt);
+        k_yee_fused<float><<<grd, 256, lds, st>>>(a);
     }
     return hipGetLastError();
 }

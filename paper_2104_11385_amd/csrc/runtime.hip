@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <map>
+
 #include "kernels.hpp"
 #include "runtime.hpp"
 
@@ -19,6 +21,9 @@ using namespace pb;
 namespace {
 
 thread_local std::string g_init_error;
+
+// Autotuner results, shared by contexts of the same workload signature.
+std::map<std::string, pic_tuning> g_tune_cache;
 
 const char *status_text(int code) {
     switch (code) {
@@ -182,8 +187,8 @@ GpdLaunch pic_ctx::gpd_args() const {
     L.segstart = W.segstart;
     L.tiles = d_tiles;
     for (int c = 0; c < 3; ++c) {
-        L.EB[c] = E[c];
-        L.EB[3 + c] = B[c];
+        L.EB[c] = Eb[jcur][c];
+        L.EB[3 + c] = Bb[jcur][c];
         L.J[c] = Jb[jcur][c];
     }
     for (int d = 0; d < 3; ++d) {
@@ -204,7 +209,7 @@ GpdLaunch pic_ctx::gpd_args() const {
     L.tile_base = 0;
     L.species_only = -1;
     L.queue = Q.queue;
-    L.queue_len = Q.queue_len;
+    L.queue_bounds = Q.queue_bounds;
     L.queue_head = Q.queue_head;
     L.halo = tun.halo;
     L.block = (unsigned)tun.block;
@@ -247,14 +252,22 @@ int pic_ctx::enqueue_step() {
         L.grid = (unsigned)ntiles;
         HIPC(launch_gpd(prec, order, L, st));
     } else {
-        HIPC(launch_set_int(Q.queue_head, 0, st));
+        HIPC(launch_reset_heads(Q.queue_head, st));
         L.grid = (unsigned)(n_cu * std::max(1, tun.blocks_per_cu));
         HIPC(launch_gpd(prec, order, L, st));
     }
     if ((rc = time_end())) return rc;
     if ((rc = time_begin(1))) return rc;
-    void *F[9] = {E[0], E[1], E[2], B[0], B[1], B[2], Jb[jcur][0], Jb[jcur][1], Jb[jcur][2]};
-    HIPC(launch_yee(prec, F, Jb[1 - jcur], n, dt, st));
+    YeeBuffers Y;
+    for (int c = 0; c < 3; ++c) {
+        Y.E[c] = Eb[jcur][c];
+        Y.B[c] = Bb[jcur][c];
+        Y.J[c] = Jb[jcur][c];
+        Y.Eo[c] = Eb[1 - jcur][c];
+        Y.Bo[c] = Bb[1 - jcur][c];
+        Y.Z[c] = Jb[1 - jcur][c];
+    }
+    HIPC(launch_yee(prec, Y, n, dt, st));
     if ((rc = time_end())) return rc;
     return PIC_OK;
 }
@@ -537,8 +550,9 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
     size_t fb = N * (size_t)c->prec;
     for (int k = 0; k < 3; ++k) {
-        if ((rc = c->dalloc(&c->E[k], fb)) || (rc = c->dalloc(&c->B[k], fb)) || (rc = c->dalloc(&c->Jb[0][k], fb)) ||
-            (rc = c->dalloc(&c->Jb[1][k], fb)))
+        if ((rc = c->dalloc(&c->Eb[0][k], fb)) || (rc = c->dalloc(&c->Bb[0][k], fb)) ||
+            (rc = c->dalloc(&c->Eb[1][k], fb)) || (rc = c->dalloc(&c->Bb[1][k], fb)) ||
+            (rc = c->dalloc(&c->Jb[0][k], fb)) || (rc = c->dalloc(&c->Jb[1][k], fb)))
             return init_fail(c, rc, "");
     }
     for (int b = 0; b < 2; ++b) {
@@ -558,10 +572,10 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
             return init_fail(c, rc, "");
     }
     c->Q.ncls = 64;
-    if ((rc = c->dalloc((void **)&c->Q.cls_cnt, sizeof(int) * c->Q.ncls)) ||
-        (rc = c->dalloc((void **)&c->Q.cursor, sizeof(int) * c->Q.ncls)) ||
-        (rc = c->dalloc((void **)&c->Q.queue_len, sizeof(int))) ||
-        (rc = c->dalloc((void **)&c->Q.queue_head, sizeof(int))))
+    if ((rc = c->dalloc((void **)&c->Q.cls_cnt, sizeof(int) * kSubQueues * c->Q.ncls)) ||
+        (rc = c->dalloc((void **)&c->Q.cursor, sizeof(int) * kSubQueues * c->Q.ncls)) ||
+        (rc = c->dalloc((void **)&c->Q.queue_bounds, sizeof(int) * (kSubQueues + 1))) ||
+        (rc = c->dalloc((void **)&c->Q.queue_head, sizeof(int) * kSubQueues)))
         return init_fail(c, rc, "");
     if ((rc = c->dalloc((void **)&c->d_cycles, 8 * (size_t)n_boxes)) ||
         (rc = c->dalloc((void **)&c->d_rtc, 8 * (size_t)n_boxes)) ||
@@ -592,13 +606,14 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     // fields: E = J = 0, B = b_ext (stored as B - b_ext: the uniform part is
     // added at the gather, so single precision keeps the self-field's digits)
     for (int k = 0; k < 3; ++k) {
-        if (launch_fill_f(c->prec, c->E[k], 0.0, N, c->st) || launch_fill_f(c->prec, c->B[k], 0.0, N, c->st) ||
+        if (launch_fill_f(c->prec, c->Eb[0][k], 0.0, N, c->st) || launch_fill_f(c->prec, c->Bb[0][k], 0.0, N, c->st) ||
+            launch_fill_f(c->prec, c->Eb[1][k], 0.0, N, c->st) || launch_fill_f(c->prec, c->Bb[1][k], 0.0, N, c->st) ||
             launch_fill_f(c->prec, c->Jb[0][k], 0.0, N, c->st) || launch_fill_f(c->prec, c->Jb[1][k], 0.0, N, c->st))
             return init_fail(c, PIC_EDEVICE, "field initialisation failed");
     }
     if (launch_fill_u64(c->d_cycles, n_boxes, c->st) || launch_fill_u64(c->d_rtc, n_boxes, c->st) ||
         launch_fill_u32((uint32_t *)c->d_slow, 1, c->st) ||
-        launch_fill_u32((uint32_t *)c->Q.cls_cnt, (size_t)c->Q.ncls, c->st))
+        launch_fill_u32((uint32_t *)c->Q.cls_cnt, (size_t)kSubQueues * c->Q.ncls, c->st))
         return init_fail(c, PIC_EDEVICE, "counter initialisation failed");
 
     // particles: on-device Philox loader, species after species
@@ -713,6 +728,169 @@ PIC_API int pic_set_tuning(pic_ctx *ctx, const pic_tuning *t) {
         if (e != hipSuccess) return ctx->hip_fail(e, "kernel attribute setup");
     }
     return ctx->sort_now();
+}
+
+// Copy of the mutable state (particles, fields, cost counters) used by the
+// autotuner so that its trial steps leave the simulation untouched.
+struct StateBackup {
+    std::vector<void *> bufs;
+    ~StateBackup() {
+        for (void *p : bufs) (void)hipFree(p);
+    }
+};
+
+static int copy_state(pic_ctx *c, StateBackup &bk, bool save) {
+    size_t m = (size_t)c->np, N = (size_t)c->n[0] * c->n[1] * c->n[2], fb = N * c->prec;
+    const ParticlesRaw &R = c->P[c->pcur];
+    struct Item {
+        void *dev;
+        size_t bytes;
+    };
+    std::vector<Item> items = {{R.cell, 4 * m}, {R.id, 8 * m}, {R.sp, m}, {R.w, m * c->prec}};
+    for (int d = 0; d < 3; ++d) {
+        items.push_back({R.f[d], m * c->prec});
+        items.push_back({R.u[d], m * c->prec});
+        items.push_back({c->Eb[c->jcur][d], fb});
+        items.push_back({c->Bb[c->jcur][d], fb});
+        items.push_back({c->Jb[0][d], fb});
+        items.push_back({c->Jb[1][d], fb});
+    }
+    items.push_back({c->d_cycles, 8 * (size_t)c->nb});
+    items.push_back({c->d_rtc, 8 * (size_t)c->nb});
+    if (save) {
+        for (auto &it : items) {
+            void *p = nullptr;
+            hipError_t e = hipMalloc(&p, std::max<size_t>(16, it.bytes));
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return c->fail(PIC_ENOMEM, "autotune: no memory for a state copy");
+            }
+            bk.bufs.push_back(p);
+        }
+    }
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (!items[i].bytes) continue;
+        hipError_t e = save ? hipMemcpyAsync(bk.bufs[i], items[i].dev, items[i].bytes, hipMemcpyDeviceToDevice, c->st)
+                            : hipMemcpyAsync(items[i].dev, bk.bufs[i], items[i].bytes, hipMemcpyDeviceToDevice, c->st);
+        if (e != hipSuccess) return c->hip_fail(e, "autotune state copy");
+    }
+    hipError_t e = hipStreamSynchronize(c->st);
+    return e == hipSuccess ? PIC_OK : c->hip_fail(e, "autotune sync");
+}
+
+static std::string tune_key(const pic_ctx *c) {
+    // box-size mix, particle-count bucket, order, precision, launch mode
+    std::map<std::string, int> sizes;
+    for (const pic_box &b : c->boxes)
+        sizes[std::to_string(b.hi[0] - b.lo[0]) + "x" + std::to_string(b.hi[1] - b.lo[1]) + "x" +
+              std::to_string(b.hi[2] - b.lo[2])] += 1;
+    std::string k;
+    for (auto &kv : sizes) k += kv.first + ":" + std::to_string(kv.second) + ",";
+    int bucket = 0;
+    for (int64_t v = c->np; v > 1; v >>= 1) ++bucket;
+    return k + "|np2^" + std::to_string(bucket) + "|m" + std::to_string(c->order) + "|p" + std::to_string(c->prec) +
+           "|mode" + std::to_string(c->mode) + "|nsp" + std::to_string(c->nsp);
+}
+
+PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *ms_per_step) {
+    CHECK_CTX(ctx);
+    if (steps < 1) return ctx->fail(PIC_EINVAL, "steps must be >= 1");
+    std::string key = tune_key(ctx);
+    auto hit = g_tune_cache.find(key);
+    if (hit != g_tune_cache.end()) {
+        int rc = pic_set_tuning(ctx, &hit->second);
+        if (rc) return rc;
+        if (best) *best = hit->second;
+        if (ms_per_step) *ms_per_step = -1.0;
+        return PIC_OK;
+    }
+    // candidates: every compiled tile that fits, two block sizes; then chunk
+    // and residency for the persistent queue around the best of those
+    std::vector<pic_tuning> cand;
+    const int tiles[4][3] = {{8, 4, 4}, {4, 4, 4}, {8, 8, 4}, {8, 8, 8}};
+    pic_tuning base = ctx->tun;
+    for (auto &t : tiles) {
+        bool ok = gpd_lds_bytes(ctx->prec, ctx->order, t, 1) <= 160 * 1024;
+        for (int b = 0; b < ctx->nb && ok; ++b)
+            for (int d = 0; d < 3; ++d)
+                if ((ctx->boxes[b].hi[d] - ctx->boxes[b].lo[d]) % t[d]) ok = false;
+        if (!ok) continue;
+        for (int blk : {256, 512}) {
+            pic_tuning c = base;
+            std::memcpy(c.tile, t, sizeof(int) * 3);
+            c.block = blk;
+            cand.push_back(c);
+        }
+    }
+    if (cand.empty()) return ctx->fail(PIC_EUNSUPPORTED, "no compiled tile fits these boxes");
+    StateBackup bk;
+    int rc = copy_state(ctx, bk, true);
+    if (rc) return rc;
+    int saved_since_sort = ctx->steps_since_sort, saved_jcur = ctx->jcur;
+    int64_t saved_step = ctx->step_no;
+    bool saved_graph = ctx->use_graph, saved_timing = ctx->timing;
+    ctx->use_graph = false;
+    ctx->timing = false;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return ctx->fail(PIC_EDEVICE, "autotune: hipEventCreate");
+    auto trial = [&](const pic_tuning &t, double &ms) -> int {
+        int r = copy_state(ctx, bk, false);
+        if (r) return r;
+        ctx->jcur = saved_jcur;
+        r = pic_set_tuning(ctx, &t);
+        if (r) return r;
+        if ((r = ctx->step(1))) return r;
+        if (hipEventRecord(a, ctx->st) != hipSuccess) return ctx->fail(PIC_EDEVICE, "event");
+        if ((r = ctx->step(steps))) return r;
+        if (hipEventRecord(b, ctx->st) != hipSuccess || hipEventSynchronize(b) != hipSuccess)
+            return ctx->fail(PIC_EDEVICE, "event");
+        float f = 0.f;
+        (void)hipEventElapsedTime(&f, a, b);
+        ms = f / steps;
+        return PIC_OK;
+    };
+    pic_tuning win = cand[0];
+    double win_ms = 1e30;
+    for (auto &t : cand) {
+        double ms;
+        if ((rc = trial(t, ms))) break;
+        if (ms < win_ms) {
+            win_ms = ms;
+            win = t;
+        }
+    }
+    if (!rc && ctx->mode == PIC_LAUNCH_PERSISTENT) {
+        for (int chunk : {1024, 2048, 8192}) {
+            for (int bpc : {1, 2, 4}) {
+                pic_tuning t = win;
+                t.chunk = chunk;
+                t.blocks_per_cu = bpc;
+                double ms;
+                if ((rc = trial(t, ms))) break;
+                if (ms < win_ms) {
+                    win_ms = ms;
+                    win = t;
+                }
+            }
+            if (rc) break;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    if ((rc = copy_state(ctx, bk, false))) return rc;
+    ctx->jcur = saved_jcur;
+    if ((rc = pic_set_tuning(ctx, &win))) return rc;
+    ctx->steps_since_sort = std::min(saved_since_sort, 0);
+    ctx->step_no = saved_step;
+    ctx->use_graph = saved_graph;
+    ctx->timing = saved_timing;
+    ctx->drop_graphs();
+    g_tune_cache[key] = win;
+    if (best) *best = win;
+    if (ms_per_step) *ms_per_step = win_ms;
+    return PIC_OK;
 }
 
 PIC_API int pic_reset_costs(pic_ctx *ctx) {
@@ -874,7 +1052,9 @@ PIC_API int pic_set_particles(pic_ctx *ctx, int32_t species, const double *x3, c
 PIC_API int pic_get_field(pic_ctx *ctx, int32_t comp, double *out) {
     CHECK_CTX(ctx);
     if (!out || comp < 0 || comp > 8) return ctx->fail(PIC_EINVAL, "bad component or null output");
-    const void *src = comp < 3 ? ctx->E[comp] : comp < 6 ? ctx->B[comp - 3] : ctx->Jb[1 - ctx->jcur][comp - 6];
+    const void *src = comp < 3   ? ctx->Eb[ctx->jcur][comp]
+                      : comp < 6 ? ctx->Bb[ctx->jcur][comp - 3]
+                                 : ctx->Jb[1 - ctx->jcur][comp - 6];
     size_t N = (size_t)ctx->n[0] * ctx->n[1] * ctx->n[2];
     hipError_t e = hipStreamSynchronize(ctx->st);
     if (e != hipSuccess) return ctx->hip_fail(e, "sync");
@@ -893,7 +1073,9 @@ PIC_API int pic_get_field(pic_ctx *ctx, int32_t comp, double *out) {
 PIC_API int pic_set_field(pic_ctx *ctx, int32_t comp, const double *in) {
     CHECK_CTX(ctx);
     if (!in || comp < 0 || comp > 8) return ctx->fail(PIC_EINVAL, "bad component or null input");
-    void *dst = comp < 3 ? ctx->E[comp] : comp < 6 ? ctx->B[comp - 3] : ctx->Jb[1 - ctx->jcur][comp - 6];
+    void *dst = comp < 3   ? ctx->Eb[ctx->jcur][comp]
+                : comp < 6 ? ctx->Bb[ctx->jcur][comp - 3]
+                           : ctx->Jb[1 - ctx->jcur][comp - 6];
     size_t N = (size_t)ctx->n[0] * ctx->n[1] * ctx->n[2];
     hipError_t e = hipStreamSynchronize(ctx->st);
     if (e != hipSuccess) return ctx->hip_fail(e, "sync");

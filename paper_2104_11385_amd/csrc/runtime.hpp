@@ -59,9 +59,12 @@ struct pic_ctx {
     // state
     pb::ParticlesRaw P[2];
     int pcur = 0;
-    void *E[3] = {nullptr, nullptr, nullptr}, *B[3] = {nullptr, nullptr, nullptr};
+    // E, B and J are double-buffered; index jcur holds the current E and B
+    // and is the J buffer the next step deposits into (all flip each step)
+    void *Eb[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    void *Bb[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     void *Jb[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-    int jcur = 0;  // J buffer the next step deposits into
+    int jcur = 0;
     pb::SortScratch W{};
     pb::QueueScratch Q{};
     pb::FeatScratch FS{};
@@ -72,6 +75,7 @@ struct pic_ctx {
     unsigned *d_slow = nullptr;
     std::vector<double> last_timer;      // last device-timer costs read
     std::vector<double> last_pred;       // learned prediction made for the current interval
+    double mare = -1.0;                  // last mean relative error of the learned costs
 
     // timing
     bool timing = false;

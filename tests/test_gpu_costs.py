@@ -1,0 +1,88 @@
+"""Device-timer costs and the load-balancing study on reduced workloads.
+
+Timer costs are hardware measurements, so their parity is unpinned; what is
+checked are the invariants they must satisfy: non-negative, exactly zero for
+boxes without particles, ordered like the per-box work (Spearman rho >= 0.9
+against particle counts when boxes carry different ppc), and consistent
+between the two clocks.
+"""
+import numpy as np
+import pytest
+from scipy.stats import spearmanr
+
+import picsynth
+from tests._util import make_ctx
+
+pytestmark = pytest.mark.gpu
+
+
+def uneven_workload(seed=3):
+    n = (64, 64, 64)
+    boxes = picsynth.uniform_boxes(n, 16)
+    ppc = picsynth.lognormal_box_ppc(len(boxes), seed, cap=24)
+    ppc[:4] = 0                                     # a few empty boxes
+    sp = [picsynth.Species("electrons", -1.0, 1.0, picsynth.N0_DEFAULT, box_ppc=ppc, u_th=(0.01,) * 3)]
+    return picsynth.Workload("uneven", n, boxes, sp, dt=0.5, order=2, precision=4, seed=seed)
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_timer_cost_invariants(mode):
+    from paper_2104_11385_amd import picbal as pb
+    wl = uneven_workload()
+    ctx = make_ctx(wl, load=True)
+    ctx.set_launch_mode(mode, False)
+    ctx.step(2)
+    ctx.reset_costs()
+    ctx.step(5)
+    cyc, used = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
+    rtc, _ = ctx.box_costs(pb.PIC_COST_DEVICE_RTC)
+    counts = ctx.box_counts()[:, 0]
+    assert used == pb.PIC_COST_DEVICE_TIMER
+    assert (cyc >= 0).all() and (rtc >= 0).all()
+    empty = counts == 0
+    assert empty.sum() >= 4
+    assert (cyc[empty] == 0).all() and (rtc[empty] == 0).all()
+    rho = spearmanr(cyc[~empty], counts[~empty]).statistic
+    assert rho >= 0.9, f"Spearman(cycles, counts) = {rho:.3f}"
+    assert spearmanr(cyc[~empty], rtc[~empty]).statistic >= 0.9
+    ctx.reset_costs()
+    c0, _ = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
+    assert (c0 == 0).all()
+
+
+def test_heuristic_costs_match_oracle_counts():
+    import oracle
+    from paper_2104_11385_amd import picbal as pb
+    wl = uneven_workload(5)
+    ctx = make_ctx(wl, load=True)
+    ctx.step(3)
+    h, used = ctx.box_costs(pb.PIC_COST_HEURISTIC)
+    assert used == pb.PIC_COST_HEURISTIC
+    x, u, w, ids = ctx.get_particles(0)
+    counts = oracle.box_counts(wl.boxes, x, np.zeros(len(w), np.int32), 1)
+    np.testing.assert_array_equal(h, oracle.heuristic(wl.boxes, counts, 0.75, 0.25))
+
+
+def small_study_workload():
+    n = (96, 96, 192)
+    lo, hi = (0, 0, 88), (96, 96, 100)
+    sp = [picsynth.Species("electrons", -1.0, 1.0, picsynth.N0_DEFAULT, ppc=8, region_lo=lo, region_hi=hi,
+                           u_th=(0.005,) * 3, u_drift=(0.0, 0.0, 0.08)),
+          picsynth.Species("protons", 1.0, 1836.0, picsynth.N0_DEFAULT, ppc=8, region_lo=lo, region_hi=hi,
+                           u_drift=(0.0, 0.0, 0.08))]
+    return picsynth.Workload("study-small", n, picsynth.uniform_boxes(n, 16), sp, dt=0.5, order=2, precision=4,
+                             seed=1)
+
+
+def test_learned_costs_balance_within_3_percent_of_timer():
+    import bench
+    out = bench.lb_study(steps=80, interval=10, ranks=24, train_seeds=(11, 12), eval_seed=13,
+                         name=small_study_workload)
+    E = out["E_mean"]
+    for s in ("heuristic", "timer", "learned"):
+        for p in ("sfc", "knapsack"):
+            assert 0.0 < E[s][p] <= 1.0
+    assert out["train_loss_first_last"][1] < out["train_loss_first_last"][0]
+    for p in ("sfc", "knapsack"):
+        assert out["learned_over_timer"][p] >= 0.97, out
+    print("study:", out["E_mean"], "fallbacks", out["learned_fallbacks"])
