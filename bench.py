@@ -217,6 +217,32 @@ def ctx_for(wl, stream=None):
     return pb.pic_init(wl.n, wl.boxes, sp, wl.dt, wl.order, prec, wl.seed, b_ext=wl.b_ext, stream=stream)
 
 
+def uneven_boxes(steps=5, warmup=2):
+    """512^3 cells in 4096 mixed boxes (256 of 64^3, 1792 of 32^3, 2048 of
+    16^3) with per-box ppc = min(64, round(LogNormal(1.5, 1.2))): 1.13e9
+    electrons.  Persistent queue (graph-replayed) against one launch per box."""
+    import picsynth
+    from paper_2104_11385_amd import picbal as pb
+    wl = picsynth.config("c3")
+    n_p = picsynth.species_count(wl, 0)
+    t0 = time.perf_counter()
+    ctx = ctx_for(wl)
+    init_s = time.perf_counter() - t0
+    res = {"particles": n_p, "init_s": init_s}
+    for name, mode, graph in (("persistent", pb.PIC_LAUNCH_PERSISTENT, True), ("per_box", pb.PIC_LAUNCH_PER_BOX, False)):
+        ctx.set_launch_mode(mode, graph)
+        ctx.step(warmup)
+        ctx.sync()
+        t1 = time.perf_counter()
+        ctx.step(steps)
+        ctx.sync()
+        ms = (time.perf_counter() - t1) * 1e3 / steps
+        res[name] = {"ms_per_step": ms, "particle_steps_per_s": n_p / (ms * 1e-3)}
+    res["persistent_over_per_box"] = res["per_box"]["ms_per_step"] / res["persistent"]["ms_per_step"]
+    ctx.finalize()
+    return res
+
+
 def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, name="c4"):
     """Balancing study on the 384x384x768 / 3456-box drifting-slab workload:
     trains the learned model on two runs (seeds 4 and 6, 207,360 samples),
@@ -275,6 +301,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-lb", action="store_true", help="skip the load-balancing study")
+    ap.add_argument("--no-c3", action="store_true", help="skip the uneven-box (4096 mixed boxes) comparison")
     ap.add_argument("--lb-steps", type=int, default=300)
     args = ap.parse_args()
     if args.copy_probe:
@@ -314,6 +341,8 @@ def main():
         "yee_ms": r["yee_ms"], "slow_path_particles": r["slow_path"],
         "timer_cost_spearman_vs_count": r["timer_cost_spearman_vs_count"],
     }
+    if not args.no_c3:
+        out["uneven_boxes"] = uneven_boxes()
     if not args.no_lb:
         out["lb_study"] = lb_study(steps=args.lb_steps)
     if not args.no_cpu:

@@ -172,8 +172,8 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
  * timer cycles from the current box features; it falls back to HEURISTIC
  * when no model is loaded, or when the prediction made at the previous
  * LEARNED call missed the timer costs read since then (the interval it was
- * made for) by more than 15% mean relative error over boxes with nonzero
- * cycles.  Intended order per balancing step: read DEVICE_TIMER, reset,
+ * made for) by more than 15% relative error, sum |pred - t| / sum t over
+ * boxes.  Intended order per balancing step: read DEVICE_TIMER, reset,
  * then LEARNED.  *used_strategy (nullable) reports which strategy produced
  * the values. */
 PIC_API int pic_box_costs(pic_ctx *ctx, int32_t strategy, double *costs, int32_t *used_strategy);

@@ -347,23 +347,22 @@ static int mlp_forward(pic_ctx *ctx, const float *dX, int64_t n, float *dyhat) {
 }
 
 // Predicted cycles max(0, exp(yhat) - 1) of every box (the model is trained on
-// ln(1 + cycles) so that boxes without work are represented); falls
-// back to the heuristic when no model is loaded, or when the prediction made
-// for the interval just measured missed the measured timer costs by more than
-// 15% mean relative error.
+// ln(1 + cycles) so that boxes without work are represented); falls back to
+// the heuristic when no model is loaded, or when the prediction made for the
+// interval just measured missed the measured timer costs by more than 15%
+// relative error, sum_b |pred_b - t_b| / sum_b t_b (errors weighted by cost,
+// so a box holding a few stray particles cannot trigger the fallback alone).
 int pic_ctx::learned_costs(double *costs, int *used) {
     *used = PIC_COST_HEURISTIC;
     if (!mlp || !mlp->ready) return PIC_OK;
     bool fallback = false;
     if (last_pred.size() == (size_t)nb && last_timer.size() == (size_t)nb) {
-        double sum = 0.0;
-        int cnt = 0;
-        for (int b = 0; b < nb; ++b)
-            if (last_timer[b] > 0.0) {
-                sum += std::fabs(last_pred[b] - last_timer[b]) / last_timer[b];
-                ++cnt;
-            }
-        mare = cnt ? sum / cnt : 0.0;
+        double err = 0.0, tot = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            err += std::fabs(last_pred[b] - last_timer[b]);
+            tot += last_timer[b];
+        }
+        mare = tot > 0.0 ? err / tot : 0.0;
         fallback = mare > 0.15;
     }
     int rc = features_device();

@@ -27,6 +27,12 @@ __device__ __forceinline__ int wrap_any(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
+// Wraps i into [0, n) when it lies in [-n, 2n) (one conditional step).
+__device__ __forceinline__ int wrap_near(int i, int n) {
+    i = i < 0 ? i + n : i;
+    return i >= n ? i - n : i;
+}
+
 // Wraps a tile-relative coordinate r into [-h, n - h).
 __device__ __forceinline__ int wrap_rel(int r, int h, int n) {
     int t = r + h;
@@ -35,6 +41,13 @@ __device__ __forceinline__ int wrap_rel(int r, int h, int n) {
     if (t < 0 || t >= n) t = wrap_any(t, n);
     return t - h;
 }
+
+// 1/sqrt(x) and 1/x: the hardware approximations (about 1 ulp) in single
+// precision, correctly rounded operations in double precision.
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
 
 template <typename real>
 __device__ __forceinline__ void atomic_add_global(real *p, real v) {
@@ -540,17 +553,28 @@ __device__ __forceinline__ void gather6(const Acc &F, const GatherW<real, M> W[3
 // a particle that keeps its reference node in every dimension has all its
 // weight on the first M + 1 nodes and uses L = M + 1 (the last running sum
 // along each axis is then zero by construction and is not deposited).
+// The transverse factor of the density decomposition,
+//   S0_u S0_v + (dS_u S0_v + S0_u dS_v) / 2 + dS_u dS_v / 3,
+// equals A_u S0_v + B_u dS_v with A = S0 + dS/2 and B = S0/2 + dS/3; the
+// charge factor -q w / dt is folded into A and B.
 template <typename real, int M, int L, typename Acc>
 __device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real coef) {
     const real h = (real)0.5, third = (real)(1.0 / 3.0);
+    real Ax[L], Bx[L], Ay[L], By[L];
+#pragma unroll
+    for (int a = 0; a < L; ++a) {
+        Ax[a] = coef * (W[0].S0[a] + h * W[0].dS[a]);
+        Bx[a] = coef * (h * W[0].S0[a] + third * W[0].dS[a]);
+        Ay[a] = coef * (W[1].S0[a] + h * W[1].dS[a]);
+        By[a] = coef * (h * W[1].S0[a] + third * W[1].dS[a]);
+    }
     J.begin(W[0].s, W[1].s, W[2].s);
-    // Jx: running sum along x (coef folded into the transverse factor)
+    // Jx: running sum along x of dSx * (A_y S0_z + B_y dS_z)
 #pragma unroll
     for (int c = 0; c < L; ++c)
 #pragma unroll
         for (int b = 0; b < L; ++b) {
-            real in = coef * (W[1].S0[b] * W[2].S0[c] + h * (W[1].dS[b] * W[2].S0[c] + W[1].S0[b] * W[2].dS[c]) +
-                              third * W[1].dS[b] * W[2].dS[c]);
+            real in = Ay[b] * W[2].S0[c] + By[b] * W[2].dS[c];
             real acc = (real)0;
 #pragma unroll
             for (int a = 0; a < L - 1; ++a) {
@@ -558,13 +582,12 @@ __device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real 
                 J.add(0, a, b, c, acc);
             }
         }
-    // Jy: running sum along y
+    // Jy: running sum along y of dSy * (A_x S0_z + B_x dS_z)
 #pragma unroll
     for (int c = 0; c < L; ++c)
 #pragma unroll
         for (int a = 0; a < L; ++a) {
-            real in = coef * (W[0].S0[a] * W[2].S0[c] + h * (W[0].dS[a] * W[2].S0[c] + W[0].S0[a] * W[2].dS[c]) +
-                              third * W[0].dS[a] * W[2].dS[c]);
+            real in = Ax[a] * W[2].S0[c] + Bx[a] * W[2].dS[c];
             real acc = (real)0;
 #pragma unroll
             for (int b = 0; b < L - 1; ++b) {
@@ -572,13 +595,12 @@ __device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real 
                 J.add(1, a, b, c, acc);
             }
         }
-    // Jz: running sum along z
+    // Jz: running sum along z of dSz * (A_x S0_y + B_x dS_y)
 #pragma unroll
     for (int b = 0; b < L; ++b)
 #pragma unroll
         for (int a = 0; a < L; ++a) {
-            real in = coef * (W[0].S0[a] * W[1].S0[b] + h * (W[0].dS[a] * W[1].S0[b] + W[0].S0[a] * W[1].dS[b]) +
-                              third * W[0].dS[a] * W[1].dS[b]);
+            real in = Ax[a] * W[1].S0[b] + Bx[a] * W[1].dS[b];
             real acc = (real)0;
 #pragma unroll
             for (int c = 0; c < L - 1; ++c) {
@@ -652,15 +674,32 @@ struct GlobJ {
     }
 };
 
+// One particle's state as loaded from HBM.
+template <typename real>
+struct PState {
+    uint32_t cell;
+    real f[3], u[3], w;
+    __device__ __forceinline__ void load(const Particles<real> &P, int p) {
+        cell = P.cell[p];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f[d] = P.f[d][p];
+            u[d] = P.u[d][p];
+        }
+        w = P.w[p];
+    }
+};
+
 template <typename real, int M, int TX, int TY, int TZ, int H>
-__device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, const TileDesc &td, real hq,
-                                              real cq, const real *sEB, double *sJ, unsigned &nslow) {
+__device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, const PState<real> &ps,
+                                              const TileDesc &td, real hq, real cq, const real *sEB, double *sJ,
+                                              unsigned &nslow) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
     int c[3];
-    unpack_cell(A.P.cell[p], c[0], c[1], c[2]);
-    real f[3] = {A.P.f[0][p], A.P.f[1][p], A.P.f[2][p]};
-    real u[3] = {A.P.u[0][p], A.P.u[1][p], A.P.u[2][p]};
-    real w = A.P.w[p];
+    unpack_cell(ps.cell, c[0], c[1], c[2]);
+    real f[3] = {ps.f[0], ps.f[1], ps.f[2]};
+    real u[3] = {ps.u[0], ps.u[1], ps.u[2]};
+    real w = ps.w;
 
     // reference point: cell (order 1) or nearest node (order 2)
     int ref[3];
@@ -711,17 +750,17 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
 
     // relativistic Boris rotation
     real um[3] = {u[0] + hq * EB[0], u[1] + hq * EB[1], u[2] + hq * EB[2]};
-    real ig = (real)1 / sqrt((real)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    real ig = rsqrt_r((real)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
     real t[3] = {hq * EB[3] * ig, hq * EB[4] * ig, hq * EB[5] * ig};
     real t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-    real sf = (real)2 / ((real)1 + t2);
+    real sf = (real)2 * rcp_r((real)1 + t2);
     real s[3] = {sf * t[0], sf * t[1], sf * t[2]};
     real up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]), um[1] + (um[2] * t[0] - um[0] * t[2]),
                   um[2] + (um[0] * t[1] - um[1] * t[0])};
     u[0] = um[0] + (up[1] * s[2] - up[2] * s[1]) + hq * EB[0];
     u[1] = um[1] + (up[2] * s[0] - up[0] * s[2]) + hq * EB[1];
     u[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + hq * EB[2];
-    real gi = (real)1 / sqrt((real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    real gi = rsqrt_r((real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     real D[3] = {A.dt * u[0] * gi, A.dt * u[1] * gi, A.dt * u[2] * gi};
 
     // Esirkepov deposit
@@ -787,6 +826,9 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nsp = A.nsp;
     const int home = blockIdx.x % kSubQueues;  // blocks are dealt round-robin over the XCDs
+    // windows reach at most JX cells; one conditional wrap suffices unless the
+    // domain is smaller than a window
+    const bool small = A.n[0] < C::JX || A.n[1] < C::JY || A.n[2] < C::JZ;
     int sq = 0;                                // sub-queues already found empty (thread 0)
 
     for (int iter = 0;; ++iter) {
@@ -836,9 +878,16 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             int r2 = r / C::EX;
             int ly = r2 % C::EY;
             int lz = r2 / C::EY;
-            int gx = wrap_any(td.x0 - H - C::RL_EB + lx, A.n[0]);
-            int gy = wrap_any(td.y0 - H - C::RL_EB + ly, A.n[1]);
-            int gz = wrap_any(td.z0 - H - C::RL_EB + lz, A.n[2]);
+            int gx = td.x0 - H - C::RL_EB + lx, gy = td.y0 - H - C::RL_EB + ly, gz = td.z0 - H - C::RL_EB + lz;
+            if (small) {
+                gx = wrap_any(gx, A.n[0]);
+                gy = wrap_any(gy, A.n[1]);
+                gz = wrap_any(gz, A.n[2]);
+            } else {
+                gx = wrap_near(gx, A.n[0]);
+                gy = wrap_near(gy, A.n[1]);
+                gz = wrap_near(gz, A.n[2]);
+            }
             sEB[i] = A.EB[comp][gx + (size_t)A.n[0] * (gy + (size_t)A.n[1] * gz)];
         }
         for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = 0.0;
@@ -856,8 +905,16 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             int sb = max(pbeg, A.segstart[tile * nsp + s]);
             int se = min(pend, A.segstart[tile * nsp + s + 1]);
             real hq = A.h[s], cq = A.coefq[s];
-            for (int p = sb + tid; p < se; p += nthr)
-                push_particle<real, M, TX, TY, TZ, H>(A, p, td, hq, cq, sEB, sJ, nslow);
+            // the next particle's loads are issued before this one is computed
+            int p = sb + tid;
+            PState<real> cur;
+            if (p < se) cur.load(A.P, p);
+            for (; p < se; p += nthr) {
+                PState<real> nxt;
+                if (p + nthr < se) nxt.load(A.P, p + nthr);
+                push_particle<real, M, TX, TY, TZ, H>(A, p, cur, td, hq, cq, sEB, sJ, nslow);
+                cur = nxt;
+            }
         }
         unsigned long long c1 = clock64(), r1 = wall_clock64();
         if ((tid & 63) == 0) {
@@ -877,9 +934,16 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 int r2 = r / C::JX;
                 int ly = r2 % C::JY;
                 int lz = r2 / C::JY;
-                int gx = wrap_any(td.x0 - H - C::RL_J + lx, A.n[0]);
-                int gy = wrap_any(td.y0 - H - C::RL_J + ly, A.n[1]);
-                int gz = wrap_any(td.z0 - H - C::RL_J + lz, A.n[2]);
+                int gx = td.x0 - H - C::RL_J + lx, gy = td.y0 - H - C::RL_J + ly, gz = td.z0 - H - C::RL_J + lz;
+                if (small) {
+                    gx = wrap_any(gx, A.n[0]);
+                    gy = wrap_any(gy, A.n[1]);
+                    gz = wrap_any(gz, A.n[2]);
+                } else {
+                    gx = wrap_near(gx, A.n[0]);
+                    gy = wrap_near(gy, A.n[1]);
+                    gz = wrap_near(gz, A.n[2]);
+                }
                 atomic_add_global(&A.J[comp][gx + (size_t)A.n[0] * (gy + (size_t)A.n[1] * gz)], v);
             }
         }

@@ -16,12 +16,13 @@ from tests._util import make_ctx
 pytestmark = pytest.mark.gpu
 
 
-def uneven_workload(seed=3):
+def uneven_workload(seed=3, u_th=0.0):
+    # cold by default: with E = B = 0 nothing moves, so empty boxes stay empty
     n = (64, 64, 64)
     boxes = picsynth.uniform_boxes(n, 16)
     ppc = picsynth.lognormal_box_ppc(len(boxes), seed, cap=24)
     ppc[:4] = 0                                     # a few empty boxes
-    sp = [picsynth.Species("electrons", -1.0, 1.0, picsynth.N0_DEFAULT, box_ppc=ppc, u_th=(0.01,) * 3)]
+    sp = [picsynth.Species("electrons", -1.0, 1.0, picsynth.N0_DEFAULT, box_ppc=ppc, u_th=(u_th,) * 3)]
     return picsynth.Workload("uneven", n, boxes, sp, dt=0.5, order=2, precision=4, seed=seed)
 
 
@@ -53,7 +54,7 @@ def test_timer_cost_invariants(mode):
 def test_heuristic_costs_match_oracle_counts():
     import oracle
     from paper_2104_11385_amd import picbal as pb
-    wl = uneven_workload(5)
+    wl = uneven_workload(5, u_th=0.02)
     ctx = make_ctx(wl, load=True)
     ctx.step(3)
     h, used = ctx.box_costs(pb.PIC_COST_HEURISTIC)

@@ -1,0 +1,57 @@
+"""The balancing study's bookkeeping, on hand-made cost records (no GPU).
+
+A mapping decided at interval boundary t_i governs interval i and is judged
+by the cycles measured in interval i; the timer strategy can only use the
+interval that just ended (i-1), the heuristic and the learned model use the
+state at t_i."""
+import numpy as np
+
+import picsynth
+from paper_2104_11385_amd import lb_study as S
+from paper_2104_11385_amd import picbal as pb
+
+
+def _rec(timer, heur, learned=None):
+    nint = len(timer)
+    rec = {"timer": np.array(timer, dtype=float), "heuristic": np.array(heur, dtype=float),
+           "feat": np.zeros((nint + 1, len(timer[0]), 16), np.float32),
+           "counts": np.zeros((nint + 1, len(timer[0]))), "learned": np.array(learned if learned else []),
+           "learned_used": np.array([])}
+    return rec
+
+
+def test_timer_strategy_lags_one_interval():
+    boxes = picsynth.uniform_boxes((64, 16, 16), 16)      # 4 boxes in a row
+    # the load moves from box 0 to box 3 between intervals
+    timer = [[8, 1, 1, 1], [1, 1, 1, 8], [1, 1, 1, 8]]
+    heur = [[8, 1, 1, 1], [1, 1, 1, 8], [1, 1, 1, 8], [1, 1, 1, 8]]
+    E = S.evaluate(_rec(timer, heur), boxes, 2)
+    # decisions at t_1, t_2 (two rebalances)
+    assert len(E["timer"]["knapsack"]) == 2
+    # heuristic sees the new state at t_1: {8} | {1,1,1} -> E = 5.5/8
+    np.testing.assert_allclose(E["heuristic"]["knapsack"], [5.5 / 8, 5.5 / 8])
+    # timer at t_1 uses interval 0 (load on box 0): box 0 alone, boxes 1..3 together;
+    # judged on interval 1 -> loads {1} | {1+1+8}
+    rank, _ = pb.lb_distribute(np.array([8.0, 1, 1, 1]), boxes, 2, pb.LB_KNAPSACK)
+    want = pb.lb_efficiency(np.array([1.0, 1, 1, 8]), rank, 2)
+    assert E["timer"]["knapsack"][0] == want
+    assert E["timer"]["knapsack"][1] == 5.5 / 8
+
+
+def test_training_pairs_state_with_following_interval():
+    rec = _rec([[3, 0], [5, 7]], [[0, 0]] * 3)
+    rec["feat"][:, :, 0] = np.array([[10, 11], [20, 21], [30, 31]])
+    X, y = S.training_set([rec])
+    np.testing.assert_array_equal(X[:, 0], [10, 11, 20, 21])
+    np.testing.assert_allclose(y, np.log1p([3, 0, 5, 7]), rtol=1e-6)
+
+
+def test_identical_costs_give_identical_efficiency():
+    boxes = picsynth.uniform_boxes((64, 64, 16), 16)
+    rng = np.random.default_rng(1)
+    timer = rng.uniform(1, 5, (4, len(boxes)))
+    heur = np.vstack([timer[:1], timer])            # heuristic at t_i equals timer[i-1]
+    E = S.evaluate(_rec(timer, heur), boxes, 3)
+    for p in ("sfc", "knapsack"):
+        np.testing.assert_array_equal(E["heuristic"][p], E["timer"][p])
+        assert ((E["timer"][p] > 0) & (E["timer"][p] <= 1)).all()
