@@ -16,7 +16,7 @@
  *     threshold (Sec. 2.2, Sec. 3.2, Sec. 3.3).
  * The PIC step itself (explicit Maxwell steps, Lorentz-force push, current
  * deposition, Sec. 2.1) follows Yee (1966), Boris (1970) and Esirkepov (2001)
- * with B-spline shapes of order 1 or 2.
+ * with B-spline shapes of order 1, 2 or 3.
  *
  * Conventions used by every call:
  *   - Units: c = eps0 = mu0 = 1; cell size 1; time in cell/c.
@@ -85,7 +85,7 @@ typedef struct {
     int32_t n_cells[3];    /* domain size; periodic in every dimension;
                               n_cells[0], n_cells[1] <= 2048, n_cells[2] <= 1024 */
     double dt;             /* time step in cell/c; must satisfy dt < 1/sqrt(3)  */
-    int32_t shape_order;   /* 1 (linear) or 2 (quadratic) B-spline shapes       */
+    int32_t shape_order;   /* 1 (linear), 2 (quadratic) or 3 (cubic) B-splines  */
     int32_t precision;     /* PIC_FP32 or PIC_FP64 for particles and fields     */
     uint64_t seed;         /* Philox4x32-10 seed of the on-device loader        */
     double w_particle;     /* heuristic weights; the paper's 0.75 / 0.25        */

@@ -43,6 +43,7 @@ struct SortScratch {
     int *segstart;            // [nseg + 1]
     uint32_t *key, *rank;     // [capacity]
     uint32_t *table;          // [capacity]
+    int *bsum, *boff;         // [nseg / 1024 + 2] block sums for the segment scan
 };
 
 struct QueueScratch {

@@ -270,6 +270,27 @@ __global__ void k_scan_single(const int *in, int *out, int n) {
     if (threadIdx.x == 0) out[n] = tot;
 }
 
+// Multi-block exclusive scan in three launches: block sums, a scan of the
+// sums, and block-local scans offset by them.  Blocks of 1024 elements.
+__global__ void k_scan_bsum(const int *in, int n, int *bsum) {
+    __shared__ int sh[17];
+    int i = blockIdx.x * 1024 + threadIdx.x;
+    int v = i < n ? in[i] : 0;
+    int tot;
+    (void)block_excl_scan(v, sh, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_apply(const int *in, int n, const int *boff, int *out) {
+    __shared__ int sh[17];
+    int i = blockIdx.x * 1024 + threadIdx.x;
+    int v = i < n ? in[i] : 0;
+    int tot;
+    int ex = block_excl_scan(v, sh, tot);
+    if (i < n) out[i] = ex + boff[blockIdx.x];
+    if (i == n - 1) out[n] = ex + v + boff[blockIdx.x];
+}
+
 __global__ void k_sort_levels(const uint32_t *cellcnt, const uint32_t *cellstart, const int *segstart,
                               uint32_t *table, int Tvol) {
     __shared__ int sh[17];
@@ -404,8 +425,8 @@ __global__ void k_fill(T *a, T v, size_t n) {
 // halo H on both sides.
 template <typename real, int M, int TX, int TY, int TZ, int H>
 struct Cfg {
-    static constexpr int RL_EB = (M == 2) ? 2 : 1, RH_EB = 1;
-    static constexpr int RL_J = (M == 2) ? 2 : 1, RH_J = 2;
+    static constexpr int RL_EB = (M == 1) ? 1 : 2, RH_EB = (M == 3) ? 2 : 1;
+    static constexpr int RL_J = (M == 1) ? 1 : 2, RH_J = (M == 3) ? 3 : 2;
     static constexpr int EX = TX + 2 * H + RL_EB + RH_EB;
     static constexpr int EY = TY + 2 * H + RL_EB + RH_EB;
     static constexpr int EZ = TZ + 2 * H + RL_EB + RH_EB;
@@ -427,8 +448,24 @@ template <typename real, int M>
 struct GatherW {
     real wn[M + 1], wh[M + 1];
     int bh;
+    // cubic B-spline weights of the nodes at -1, 0, 1, 2 from a point at
+    // fraction t in [0, 1) of its cell
+    __device__ __forceinline__ static void cubic(real t, real *w) {
+        const real sixth = (real)(1.0 / 6.0), tt = (real)(2.0 / 3.0);
+        real u = (real)1 - t;
+        w[0] = sixth * u * u * u;
+        w[1] = tt - t * t + (real)0.5 * t * t * t;
+        w[2] = tt - u * u + (real)0.5 * u * u * u;
+        w[3] = sixth * t * t * t;
+    }
     __device__ __forceinline__ void set(real d) {
-        if (M == 1) {
+        if (M == 3) {
+            // reference is the cell; d = offset in [0, 1)
+            cubic(d, wn);
+            bool up = d >= (real)0.5;
+            cubic(up ? d - (real)0.5 : d + (real)0.5, wh);
+            bh = up ? -1 : -2;
+        } else if (M == 1) {
             wn[0] = (real)1 - d;
             wn[1] = d;
             bool up = d >= (real)0.5;
@@ -462,7 +499,46 @@ struct DepW {
     bool moved;  // the particle left its reference cell / node this step
     __device__ __forceinline__ void set(real d0, real D) {
         real d1 = d0 + D;
-        if (M == 1) {
+        if (M == 3) {
+            // reference is the cell, d0 in [0, 1); nodes at offsets -1..2
+            int k = (d1 >= (real)1) - (d1 < (real)0);
+            real f1 = d1 - (real)k;
+            bool km = k < 0, kp = k > 0;
+            real o[4], n[4];
+            GatherW<real, 3>::cubic(d0, o);
+            GatherW<real, 3>::cubic(f1, n);
+            // window of 5 nodes from offset s = min(0, k) - 1
+            S0[0] = km ? (real)0 : o[0];
+            S0[1] = km ? o[0] : o[1];
+            S0[2] = km ? o[1] : o[2];
+            S0[3] = km ? o[2] : o[3];
+            S0[4] = km ? o[3] : (real)0;
+            real s1[5];
+            s1[0] = kp ? (real)0 : n[0];
+            s1[1] = kp ? n[0] : n[1];
+            s1[2] = kp ? n[1] : n[2];
+            s1[3] = kp ? n[2] : n[3];
+            s1[4] = kp ? n[3] : (real)0;
+#pragma unroll
+            for (int a = 0; a < 5; ++a) dS[a] = s1[a] - S0[a];
+            if (k == 0) {
+                // differences formed from the displacement D = d1 - d0:
+                // with Q(a, b) = a^2 + ab + b^2 and g = 1 - d,
+                //   node -1: -D Q(g0, g1) / 6        node 2: D Q(d0, d1) / 6
+                //   node  0: -D (d0 + d1) + D Q(d0, d1) / 2
+                //   node  1:  D (g0 + g1) - D Q(g0, g1) / 2
+                const real sixth = (real)(1.0 / 6.0), h = (real)0.5;
+                real g0 = (real)1 - d0, g1 = (real)1 - d1;
+                real qf = d0 * d0 + d0 * d1 + d1 * d1, qg = g0 * g0 + g0 * g1 + g1 * g1;
+                dS[0] = -D * sixth * qg;
+                dS[1] = -D * (d0 + d1) + h * D * qf;
+                dS[2] = D * (g0 + g1) - h * D * qg;
+                dS[3] = D * sixth * qf;
+                dS[4] = (real)0;
+            }
+            s = km ? -2 : -1;
+            moved = k != 0;
+        } else if (M == 1) {
             int k = (d1 >= (real)1) - (d1 < (real)0);
             real f1 = d1 - (real)k;
             bool km = k < 0, kp = k > 0;
@@ -519,7 +595,7 @@ struct DepW {
 // where (i,j,k) are offsets from the particle's reference.
 template <typename real, int M, typename Acc>
 __device__ __forceinline__ void gather6(const Acc &F, const GatherW<real, M> W[3], real EB[6]) {
-    const int bn = (M == 2) ? -1 : 0;
+    const int bn = (M == 1) ? 0 : -1;
     // stagger pattern per component: 1 = half node along that axis
     const int pat[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
 #pragma unroll
@@ -643,10 +719,10 @@ struct GlobEB {
     const real *const *EB;
     int n[3], r[3];
     mutable const real *arr;
-    mutable int ix[3], iy[3], iz[3];
+    mutable int ix[4], iy[4], iz[4];
     __device__ __forceinline__ void begin(int c, int ox, int oy, int oz) const {
         arr = EB[c];
-        for (int q = 0; q < 3; ++q) {
+        for (int q = 0; q < 4; ++q) {
             ix[q] = wrap_any(r[0] + ox + q, n[0]);
             iy[q] = wrap_any(r[1] + oy + q, n[1]);
             iz[q] = wrap_any(r[2] + oz + q, n[2]);
@@ -661,9 +737,9 @@ template <typename real>
 struct GlobJ {
     real *const *J;
     int n[3], r[3];
-    int ix[4], iy[4], iz[4];
+    int ix[5], iy[5], iz[5];
     __device__ __forceinline__ void begin(int sx, int sy, int sz) {
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 5; ++q) {
             ix[q] = wrap_any(r[0] + sx + q, n[0]);
             iy[q] = wrap_any(r[1] + sy + q, n[1]);
             iz[q] = wrap_any(r[2] + sz + q, n[2]);
@@ -1230,7 +1306,14 @@ hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, i
         else k_sort_key<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(S), np, G, W.cellcnt, W.key, W.rank);
     }
     k_sort_seg<<<nts, G.Tvol, 0, st>>>(W.cellcnt, W.cellstart, W.segtot, G.Tvol);
-    k_scan_single<<<1, 1024, 0, st>>>(W.segtot, W.segstart, nts);
+    if (nts <= 4096) {
+        k_scan_single<<<1, 1024, 0, st>>>(W.segtot, W.segstart, nts);
+    } else {
+        int nblk1 = (nts + 1023) / 1024;  // <= W.scan_cap
+        k_scan_bsum<<<nblk1, 1024, 0, st>>>(W.segtot, nts, W.bsum);
+        k_scan_single<<<1, 1024, 0, st>>>(W.bsum, W.boff, nblk1);
+        k_scan_apply<<<nblk1, 1024, 0, st>>>(W.segtot, nts, W.boff, W.segstart);
+    }
     k_sort_levels<<<nts, G.Tvol, 0, st>>>(W.cellcnt, W.cellstart, W.segstart, W.table, G.Tvol);
     if (np > 0) {
         if (prec == 8)
@@ -1346,7 +1429,7 @@ bool gpd_supported(const int tile[3], int halo) {
 }
 
 size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo) {
-    int rl_eb = order == 2 ? 2 : 1, rh_eb = 1, rl_j = order == 2 ? 2 : 1, rh_j = 2;
+    int rl_eb = order == 1 ? 1 : 2, rh_eb = order == 3 ? 2 : 1, rl_j = order == 1 ? 1 : 2, rh_j = order == 3 ? 3 : 2;
     size_t neb = 1, nj = 1;
     for (int d = 0; d < 3; ++d) {
         neb *= (size_t)(tile[d] + 2 * halo + rl_eb + rh_eb);
@@ -1356,7 +1439,11 @@ size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo) {
 }
 
 hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st) {
-    if (prec == 8) return order == 2 ? gpd_tile<double, 2>(L, st) : gpd_tile<double, 1>(L, st);
+    if (prec == 8) {
+        if (order == 3) return gpd_tile<double, 3>(L, st);
+        return order == 2 ? gpd_tile<double, 2>(L, st) : gpd_tile<double, 1>(L, st);
+    }
+    if (order == 3) return gpd_tile<float, 3>(L, st);
     return order == 2 ? gpd_tile<float, 2>(L, st) : gpd_tile<float, 1>(L, st);
 }
 

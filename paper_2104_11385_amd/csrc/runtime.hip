@@ -155,6 +155,11 @@ int pic_ctx::build_tiles() {
     tile_allocs.push_back(W.segtot);
     if ((rc = dalloc((void **)&W.segstart, sizeof(int) * (W.nseg + 1)))) return rc;
     tile_allocs.push_back(W.segstart);
+    size_t nb1 = (size_t)W.nseg / 1024 + 2;
+    if ((rc = dalloc((void **)&W.bsum, sizeof(int) * nb1))) return rc;
+    tile_allocs.push_back(W.bsum);
+    if ((rc = dalloc((void **)&W.boff, sizeof(int) * (nb1 + 1)))) return rc;
+    tile_allocs.push_back(W.boff);
     int chunk = std::max(64, tun.chunk);
     size_t qmax = (size_t)ntiles + (size_t)(cap / chunk) + 1;
     if ((rc = dalloc((void **)&Q.queue, sizeof(int4) * qmax))) return rc;
@@ -416,10 +421,8 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     for (int d = 0; d < 3; ++d)
         if (grid->n_cells[d] < 1 || grid->n_cells[d] > lim[d])
             return init_fail(nullptr, PIC_EINVAL, "domain size out of range");
-    if (grid->shape_order != 1 && grid->shape_order != 2) {
-        if (grid->shape_order == 3) return init_fail(nullptr, PIC_EUNSUPPORTED, "cubic shapes are not built");
-        return init_fail(nullptr, PIC_EINVAL, "shape_order must be 1 or 2");
-    }
+    if (grid->shape_order < 1 || grid->shape_order > 3)
+        return init_fail(nullptr, PIC_EINVAL, "shape_order must be 1, 2 or 3");
     if (grid->precision != PIC_FP32 && grid->precision != PIC_FP64)
         return init_fail(nullptr, PIC_EINVAL, "precision must be PIC_FP32 or PIC_FP64");
     if (!(grid->dt > 0.0)) return init_fail(nullptr, PIC_EINVAL, "dt must be positive");

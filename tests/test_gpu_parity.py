@@ -66,7 +66,7 @@ def test_c1_ten_steps(precision):
 
 
 @pytest.mark.parametrize("precision", [8, 4])
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, 3])
 def test_random_fields_two_species(precision, order):
     wl = quad_workload(precision)
     wl.order = order
@@ -90,11 +90,12 @@ def test_launch_modes_agree_with_oracle(mode, graph):
     compare(ctx, wl, x, u, w, sp, ids, F, 7, TOL[8])
 
 
-@pytest.mark.parametrize("precision", [8, 4])
-def test_fast_particles_take_global_path(precision):
+@pytest.mark.parametrize("precision,order", [(8, 2), (4, 2), (8, 3), (4, 1)])
+def test_fast_particles_take_global_path(precision, order):
     # u_th = 0.6: particles drift several cells between sorts, beyond the
     # staged halo, and must still match through the global-memory path.
     wl = quad_workload(precision, u_th=0.6, seed=8)
+    wl.order = order
     print(f"[parity] fast particles precision={precision}", flush=True)
     ctx = make_ctx(wl, load=False)
     ctx.set_tuning(sort_interval=1000)
@@ -185,3 +186,28 @@ def test_device_loader_matches_generator(precision):
         tol = 1e-14 if precision == 8 else 1e-7
         assert np.abs(gu - hu).max() <= tol * max(1e-300, np.abs(hu).max()) + (0 if s == 0 else 1e-30)
         np.testing.assert_allclose(gw, hw, rtol=1e-7 if precision == 4 else 0)
+
+
+@pytest.mark.parametrize("mode", [2, 0])
+def test_autotune_keeps_state_and_picks_a_valid_tuning(mode):
+    # the autotuner's trial steps must leave the simulation untouched: a run
+    # with an autotune in the middle still matches the oracle step for step
+    wl = quad_workload(8, seed=31)
+    ctx = make_ctx(wl, load=False)
+    ctx.set_launch_mode(mode, False)
+    F0 = picsynth.random_fields(wl.n, 5, amp=0.03)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+    ctx.step(3)
+    t, ms = ctx.autotune(2)
+    assert ms > 0
+    assert tuple(t.tile) in {(8, 4, 4), (4, 4, 4), (8, 8, 4), (8, 8, 8)}
+    got = ctx.get_tuning()
+    assert tuple(got.tile) == tuple(t.tile) and got.block == t.block
+    ctx.step(4)
+    compare(ctx, wl, x, u, w, sp, ids, F, 7, TOL[8])
+    # a second context of the same workload reuses the cached choice
+    ctx2 = make_ctx(wl, load=False)
+    ctx2.set_launch_mode(mode, False)
+    set_state(ctx2, wl, F0)
+    t2, ms2 = ctx2.autotune(2)
+    assert ms2 == -1.0 and tuple(t2.tile) == tuple(t.tile)

@@ -41,8 +41,8 @@ def test_init_argument_errors():
         pb.pic_init(wl.n, wl.boxes, sp, 0.6, 1, pb.PIC_FP64, 1)          # CFL
     assert e.value.code == pb.PIC_ECFL
     with pytest.raises(pb.PicError) as e:
-        pb.pic_init(wl.n, wl.boxes, sp, 0.5, 3, pb.PIC_FP64, 1)          # cubic not built
-    assert e.value.code == pb.PIC_EUNSUPPORTED
+        pb.pic_init(wl.n, wl.boxes, sp, 0.5, 4, pb.PIC_FP64, 1)          # no fourth-order shapes
+    assert e.value.code == pb.PIC_EINVAL
     with pytest.raises(pb.PicError) as e:
         pb.pic_init(wl.n, wl.boxes, sp, 0.5, 1, 2, 1)                    # precision
     assert e.value.code == pb.PIC_EINVAL
