@@ -278,7 +278,25 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     summ = S.summary(E)
     fallbacks = int(sum(1 for u in rec["learned_used"] if u != pb.PIC_COST_LEARNED))
     ctx.finalize()
-    out = {"E_mean": summ, "rebalances": int(len(rec["timer"]) - 1),
+    # the balancing loop replayed on the held-out run: no balancing, one
+    # static rebalance, and dynamic rebalancing every 10/20/30 steps with
+    # 5/10/15% adoption thresholds (timer and learned costs)
+    loop = {}
+    for pname, pol in S.POLICIES.items():
+        Ev, _ = S.replay(rec, wl.boxes, ranks, pol, mode="none")
+        loop[f"{pname}/none"] = {"E_mean": float(Ev.mean()), "adoptions": 0}
+        for strat in ("timer", "learned"):
+            Ev, a = S.replay(rec, wl.boxes, ranks, pol, strategy=strat, mode="static")
+            loop[f"{pname}/{strat}/static"] = {"E_mean": float(Ev.mean()), "adoptions": a}
+            for every in (1, 2, 3):
+                for thr in (0.05, 0.10, 0.15):
+                    Ev, a = S.replay(rec, wl.boxes, ranks, pol, strategy=strat, mode="dynamic",
+                                     every=every, threshold=thr)
+                    loop[f"{pname}/{strat}/every{every * interval}/thr{int(thr * 100)}"] = {
+                        "E_mean": float(Ev.mean()), "adoptions": a}
+    # halo bytes per policy: FP32 E, B and J (9 x 4 bytes) per cross-rank cell face
+    comm = S.comm_per_policy(rec, wl.boxes, wl.n, ranks, bytes_per_face_cell=36.0)
+    out = {"E_mean": summ, "loop_replay": loop, "halo_bytes_per_rebalance_mapping": comm, "rebalances": int(len(rec["timer"]) - 1),
            "learned_over_timer": {p: summ["learned"][p] / summ["timer"][p] for p in summ["timer"]},
            "learned_minus_heuristic": {p: summ["learned"][p] - summ["heuristic"][p] for p in summ["timer"]},
            "learned_fallbacks": fallbacks, "train_samples": int(len(y)), "train_loss_first_last":

@@ -233,6 +233,17 @@ PIC_API int lb_should_adopt(double e_current, double e_proposed, double threshol
 /* Morton key of box-grid coordinates (21 bits each). */
 PIC_API uint64_t lb_morton_key(uint32_t x, uint32_t y, uint32_t z);
 
+/* Halo traffic a mapping implies (the communication the paper expects SFC
+ * to reduce, Sec. 3.3 and Sec. 6): for every face shared by two boxes on
+ * different ranks (periodic domain), each of the two ranks sends
+ * bytes_per_face_cell per cell of that face (e.g. guard depth x components
+ * x bytes).  per_rank[n_ranks] (nullable) receives each rank's bytes,
+ * *total (nullable) their sum.  PIC_EINVAL if the boxes do not tile the
+ * domain or a rank is out of range. */
+PIC_API int lb_comm_volume(const pic_box *boxes, int32_t n_boxes, const int32_t n_cells[3],
+                           const int32_t *rank_of_box, int32_t n_ranks, double bytes_per_face_cell,
+                           double *per_rank, double *total);
+
 /* ---- learned cost model ----------------------------------------------- */
 
 /* feat[n_boxes][16] (caller-owned) receives per-box features:

@@ -9,8 +9,7 @@ load-balance efficiency of Eq. 1 and the learned cost model's MLP.  It shares
 no code with the HIP library and never calls it.
 
 Every function here is pinned by tests under ``tests/`` against closed forms,
-invariants, brute force or the paper's worked example.  The one part without a
-pin is ``box_features`` feature 15 (mean |u|), which is a plain average.
+invariants, brute force, hand-computed cases or the paper's worked example.
 """
 from __future__ import annotations
 
@@ -72,6 +71,8 @@ def lib():
         L.orc_sfc.argtypes = [i32, P, P, i32, P, P]
         L.orc_knapsack.restype = ctypes.c_int
         L.orc_knapsack.argtypes = [i32, P, i32, P]
+        L.orc_comm_volume.restype = ctypes.c_int
+        L.orc_comm_volume.argtypes = [P, i32, P, P, i32, f64, P]
         L.orc_box_features.restype = ctypes.c_int
         L.orc_box_features.argtypes = [P, i32, P, i64, P, P, P, i32, i32, P]
         L.orc_mlp_nparam.restype = i32
@@ -221,6 +222,18 @@ def knapsack(costs, R):
     if rc != 0:
         raise ValueError("orc_knapsack failed")
     return rank
+
+
+def comm_volume(n, boxes, rank, R, bytes_per_face_cell=1.0):
+    """Per-rank halo bytes of a mapping (every cross-rank cell face)."""
+    n = _i64(n)
+    boxes = _i32(boxes).reshape(-1, 6)
+    per = np.zeros(int(R))
+    rc = lib().orc_comm_volume(_p(n), boxes.shape[0], _p(boxes), _p(_i32(rank)), int(R),
+                               float(bytes_per_face_cell), _p(per))
+    if rc != 0:
+        raise ValueError("boxes do not cover the domain")
+    return per
 
 
 def box_features(n, boxes, x, u, sp, nsp, order):

@@ -566,6 +566,43 @@ int orc_knapsack(int32_t nb, const double *costs, int32_t R, int32_t *rank)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Halo traffic of a distribution mapping                                     */
+/* ------------------------------------------------------------------------ */
+
+/* For every cell and each of its +x, +y, +z neighbours (periodic): if the two
+ * cells lie in boxes owned by different ranks, each of the two ranks sends
+ * `bytes` for that face.  per_rank[R] out.  Returns -1 if a cell lies in no
+ * box. */
+int orc_comm_volume(const int64_t n[3], int32_t nb, const int32_t *boxes, const int32_t *rank, int32_t R,
+                    double bytes, double *per_rank)
+{
+    size_t N = (size_t)(n[0] * n[1] * n[2]);
+    int32_t *owner = malloc(sizeof(int32_t) * N);
+    for (size_t i = 0; i < N; ++i) owner[i] = -1;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t *bx = boxes + 6 * b;
+        for (int64_t k = bx[2]; k < bx[5]; ++k)
+            for (int64_t j = bx[1]; j < bx[4]; ++j)
+                for (int64_t i = bx[0]; i < bx[3]; ++i) owner[at(n, i, j, k)] = b;
+    }
+    for (int32_t r = 0; r < R; ++r) per_rank[r] = 0.0;
+    for (int64_t k = 0; k < n[2]; ++k)
+        for (int64_t j = 0; j < n[1]; ++j)
+            for (int64_t i = 0; i < n[0]; ++i) {
+                int32_t a = owner[at(n, i, j, k)];
+                if (a < 0) { free(owner); return -1; }
+                int32_t nbr[3] = {owner[at(n, i + 1, j, k)], owner[at(n, i, j + 1, k)], owner[at(n, i, j, k + 1)]};
+                for (int d = 0; d < 3; ++d) {
+                    if (rank[a] == rank[nbr[d]]) continue;
+                    per_rank[rank[a]] += bytes;
+                    per_rank[rank[nbr[d]]] += bytes;
+                }
+            }
+    free(owner);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Per-box features for the learned cost model                                */
 /* ------------------------------------------------------------------------ */
 

@@ -202,4 +202,57 @@ PIC_API int lb_distribute(const double *costs, const pic_box *boxes, int32_t n_b
     return rc;
 }
 
+// Halo traffic of a mapping: every face shared by two boxes on different
+// ranks (the domain is periodic) costs bytes_per_face_cell per cell of face,
+// sent by each of the two ranks.  Walks the coarse grid of box corners.
+PIC_API int lb_comm_volume(const pic_box *boxes, int32_t n_boxes, const int32_t n_cells[3],
+                           const int32_t *rank_of_box, int32_t n_ranks, double bytes_per_face_cell,
+                           double *per_rank, double *total) {
+    if (!boxes || !n_cells || !rank_of_box || n_boxes < 1 || n_ranks < 1) return PIC_EINVAL;
+    int64_t g[3], cg[3];
+    for (int d = 0; d < 3; ++d) {
+        if (n_cells[d] < 1) return PIC_EINVAL;
+        int64_t v = n_cells[d];
+        for (int32_t b = 0; b < n_boxes; ++b) v = std::gcd(std::gcd(v, (int64_t)boxes[b].lo[d]), (int64_t)boxes[b].hi[d]);
+        g[d] = v;
+        cg[d] = n_cells[d] / v;
+    }
+    std::vector<int32_t> owner((size_t)(cg[0] * cg[1] * cg[2]), -1);
+    for (int32_t b = 0; b < n_boxes; ++b) {
+        if (rank_of_box[b] < 0 || rank_of_box[b] >= n_ranks) return PIC_EINVAL;
+        for (int64_t z = boxes[b].lo[2] / g[2]; z < boxes[b].hi[2] / g[2]; ++z)
+            for (int64_t y = boxes[b].lo[1] / g[1]; y < boxes[b].hi[1] / g[1]; ++y)
+                for (int64_t x = boxes[b].lo[0] / g[0]; x < boxes[b].hi[0] / g[0]; ++x) {
+                    int32_t &o = owner[(size_t)(x + cg[0] * (y + cg[1] * z))];
+                    if (o >= 0) return PIC_EINVAL;
+                    o = b;
+                }
+    }
+    for (int32_t o : owner)
+        if (o < 0) return PIC_EINVAL;
+    std::vector<double> per(n_ranks, 0.0);
+    const double area[3] = {(double)(g[1] * g[2]), (double)(g[0] * g[2]), (double)(g[0] * g[1])};
+    for (int64_t z = 0; z < cg[2]; ++z)
+        for (int64_t y = 0; y < cg[1]; ++y)
+            for (int64_t x = 0; x < cg[0]; ++x) {
+                int32_t b = owner[(size_t)(x + cg[0] * (y + cg[1] * z))];
+                int64_t nb[3][3] = {{(x + 1) % cg[0], y, z}, {x, (y + 1) % cg[1], z}, {x, y, (z + 1) % cg[2]}};
+                for (int d = 0; d < 3; ++d) {
+                    int32_t c = owner[(size_t)(nb[d][0] + cg[0] * (nb[d][1] + cg[1] * nb[d][2]))];
+                    int32_t ra = rank_of_box[b], rb = rank_of_box[c];
+                    if (ra == rb) continue;
+                    double v = area[d] * bytes_per_face_cell;
+                    per[ra] += v;
+                    per[rb] += v;
+                }
+            }
+    double tot = 0.0;
+    for (int32_t r = 0; r < n_ranks; ++r) {
+        tot += per[r];
+        if (per_rank) per_rank[r] = per[r];
+    }
+    if (total) *total = tot;
+    return PIC_OK;
+}
+
 }  // extern "C"

@@ -82,5 +82,47 @@ def evaluate(rec, boxes, n_ranks: int, predictions=None):
     return {s: {p: np.array(v) for p, v in d.items() if len(v)} for s, d in out.items()}
 
 
+def comm_per_policy(rec, boxes, n_cells, n_ranks: int, strategy="timer", bytes_per_face_cell=1.0):
+    """Mean over rebalances of the total and the largest per-rank halo traffic
+    of each policy's mappings (the communication SFC is meant to save)."""
+    out = {}
+    for pname, pol in POLICIES.items():
+        tots, mx = [], []
+        for i in range(1, len(rec["timer"])):
+            c = rec["timer"][i - 1] if strategy == "timer" else rec[strategy][i]
+            rank, _ = pb.lb_distribute(np.maximum(c, 0.0), boxes, n_ranks, pol)
+            per, tot = pb.lb_comm_volume(boxes, n_cells, rank, n_ranks, bytes_per_face_cell)
+            tots.append(tot)
+            mx.append(per.max())
+        out[pname] = {"total": float(np.mean(tots)), "max_rank": float(np.mean(mx))}
+    return out
+
+
+def replay(rec, boxes, n_ranks: int, policy: int, strategy="timer", mode="dynamic", every=1, threshold=0.10):
+    """The balancing loop replayed on recorded costs (Sec. 2.2 and Sec. 3.2).
+
+    The initial mapping is the space-filling curve with equal box costs (no
+    load information).  mode "none" keeps it; "static" adopts the strategy's
+    mapping once, at the first balancing step; "dynamic" proposes a mapping
+    every `every` intervals and adopts it when its efficiency, estimated
+    from the same costs, improves on the current mapping's by the relative
+    threshold.  Returns (E of each interval under the mapping in force, the
+    number of adoptions)."""
+    nint = len(rec["timer"])
+    nb = len(boxes)
+    mapping, _ = pb.lb_distribute(np.ones(nb), boxes, n_ranks, pb.LB_SFC)
+    E, adopted = [], 0
+    for i in range(nint):
+        if i >= 1 and mode != "none" and (mode == "dynamic" and i % every == 0 or mode == "static" and i == 1):
+            c = np.maximum(rec["timer"][i - 1] if strategy == "timer" else rec[strategy][i], 0.0)
+            proposed, e_new = pb.lb_distribute(c, boxes, n_ranks, policy)
+            e_cur = pb.lb_efficiency(c, mapping, n_ranks)
+            if mode == "static" or pb.lb_should_adopt(e_cur, e_new, threshold):
+                mapping = proposed
+                adopted += 1
+        E.append(pb.lb_efficiency(rec["timer"][i], mapping, n_ranks))
+    return np.array(E), adopted
+
+
 def summary(E):
     return {s: {p: float(v.mean()) for p, v in d.items()} for s, d in E.items() if d}

@@ -86,6 +86,7 @@ def lib():
             "lb_efficiency": (f64, [P, P, i32, i32]),
             "lb_should_adopt": (ctypes.c_int, [f64, f64, f64]),
             "lb_morton_key": (u64, [ctypes.c_uint32] * 3),
+            "lb_comm_volume": (ctypes.c_int, [P, i32, P, P, i32, f64, P, P]),
             "pic_box_features": (ctypes.c_int, [P, P]),
             "pic_mlp_nparam": (i32, []),
             "pic_mlp_train": (ctypes.c_int, [P, P, P, i64, i32, i32, P, P, u64, P]),
@@ -111,7 +112,7 @@ def exported_symbols():
     return ["pic_init", "pic_finalize", "pic_step", "pic_sync", "pic_set_launch_mode", "pic_get_tuning",
             "pic_set_tuning", "pic_autotune", "pic_box_costs", "pic_reset_costs", "pic_box_counts",
             "pic_get_particles", "pic_set_particles", "pic_get_field", "pic_set_field", "lb_distribute",
-            "lb_efficiency", "lb_should_adopt", "lb_morton_key", "pic_box_features", "pic_mlp_nparam",
+            "lb_efficiency", "lb_should_adopt", "lb_morton_key", "lb_comm_volume", "pic_box_features", "pic_mlp_nparam",
             "pic_mlp_train", "pic_mlp_predict", "pic_mlp_loss_grad", "pic_mlp_set_weights",
             "pic_mlp_get_weights", "pic_kernel_timing", "pic_kernel_times", "pic_slow_path_count",
             "pic_strerror", "pic_last_error"]
@@ -166,6 +167,18 @@ def lb_should_adopt(e_current: float, e_proposed: float, threshold: float = 0.10
 
 def lb_morton_key(x: int, y: int, z: int) -> int:
     return int(lib().lb_morton_key(int(x), int(y), int(z)))
+
+
+def lb_comm_volume(boxes, n_cells, rank_of_box, n_ranks: int, bytes_per_face_cell: float = 1.0):
+    """Returns (per-rank halo bytes, total) of a mapping."""
+    barr = boxes_array(boxes)
+    n = np.ascontiguousarray(n_cells, dtype=np.int32)
+    rank = np.ascontiguousarray(rank_of_box, dtype=np.int32)
+    per = np.zeros(int(n_ranks))
+    tot = f64(0.0)
+    _check(lib().lb_comm_volume(ctypes.cast(barr, P), len(barr), _ptr(n), _ptr(rank), int(n_ranks),
+                                float(bytes_per_face_cell), _ptr(per), ctypes.byref(tot)))
+    return per, tot.value
 
 
 # ---------------------------------------------------------------------------

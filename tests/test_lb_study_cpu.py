@@ -55,3 +55,25 @@ def test_identical_costs_give_identical_efficiency():
     for p in ("sfc", "knapsack"):
         np.testing.assert_array_equal(E["heuristic"][p], E["timer"][p])
         assert ((E["timer"][p] > 0) & (E["timer"][p] <= 1)).all()
+
+
+def test_replay_modes():
+    boxes = picsynth.uniform_boxes((64, 16, 16), 16)
+    # load sits on box 0, then moves to box 3 and stays
+    timer = [[9, 1, 1, 1], [9, 1, 1, 1], [1, 1, 1, 9], [1, 1, 1, 9], [1, 1, 1, 9]]
+    rec = _rec(timer, [[0] * 4] * 6)
+    # initial SFC of equal costs on 2 ranks: {0,1} | {2,3}
+    En, an = S.replay(rec, boxes, 2, pb.LB_KNAPSACK, mode="none")
+    np.testing.assert_allclose(En, [6 / 10] * 5)
+    assert an == 0
+    Es, as_ = S.replay(rec, boxes, 2, pb.LB_KNAPSACK, mode="static")
+    assert as_ == 1
+    # static adopts {0} | {1,2,3} from interval 0 at t_1 and keeps it
+    np.testing.assert_allclose(Es, [6 / 10, 6 / 9, 6 / 11, 6 / 11, 6 / 11])
+    Ed, ad = S.replay(rec, boxes, 2, pb.LB_KNAPSACK, mode="dynamic")
+    # dynamic follows the move one interval late (timer costs)
+    np.testing.assert_allclose(Ed, [6 / 10, 6 / 9, 6 / 11, 6 / 9, 6 / 9])
+    assert ad == 2
+    # a 100% threshold never adopts
+    Ek, ak = S.replay(rec, boxes, 2, pb.LB_KNAPSACK, mode="dynamic", threshold=1.0)
+    assert ak == 0 and np.allclose(Ek, En)

@@ -96,3 +96,42 @@ def test_threshold_matches_oracle():
         for t in (0.05, 0.10, 0.15):
             assert pb.lb_should_adopt(a, b, t) == oracle.should_adopt(a, b, t)
     assert pb.lb_should_adopt(0.5, 0.55, 0.10)
+
+
+@pytest.mark.parametrize("layout,R", [("c1", 4), ("c1", 8), ("c4", 96)])
+def test_comm_volume_matches_oracle(layout, R):
+    wl = picsynth.config(layout)
+    rng = np.random.default_rng(R)
+    costs = rng.lognormal(0.0, 1.0, len(wl.boxes))
+    for policy in (pb.LB_SFC, pb.LB_KNAPSACK):
+        rank, _ = pb.lb_distribute(costs, wl.boxes, R, policy)
+        per, tot = pb.lb_comm_volume(wl.boxes, wl.n, rank, R, 3.0)
+        if np.prod(wl.n) <= 2 ** 20:
+            want = oracle.comm_volume(wl.n, wl.boxes, rank, R, 3.0)
+            np.testing.assert_array_equal(per, want)
+        assert tot == per.sum()
+    # everything on one rank: no traffic
+    per, tot = pb.lb_comm_volume(wl.boxes, wl.n, np.zeros(len(wl.boxes), np.int32), R)
+    assert tot == 0.0
+
+
+def test_comm_volume_mixed_boxes_small():
+    # mixed 8/16-cell boxes in a 32^3 domain against the oracle's cell walk
+    boxes = []
+    for K in range(2):
+        for J in range(2):
+            for I in range(2):
+                o = np.array([I, J, K]) * 16
+                if (I + J + K) % 2 == 0:
+                    boxes.append([*o, *(o + 16)])
+                else:
+                    for dz in range(2):
+                        for dy in range(2):
+                            for dx in range(2):
+                                q = o + np.array([dx, dy, dz]) * 8
+                                boxes.append([*q, *(q + 8)])
+    boxes = np.array(boxes, dtype=np.int32)
+    rng = np.random.default_rng(3)
+    rank = rng.integers(0, 5, len(boxes)).astype(np.int32)
+    per, _ = pb.lb_comm_volume(boxes, (32, 32, 32), rank, 5, 2.0)
+    np.testing.assert_array_equal(per, oracle.comm_volume((32, 32, 32), boxes, rank, 5, 2.0))

@@ -188,3 +188,18 @@ def test_heuristic_no_fma_order():
     a = np.float64(0.1) * np.float64(123456789)
     b = np.float64(0.7) * np.float64(3)
     assert c[0] == a + b
+
+
+def test_comm_volume_by_hand():
+    # two 16^3 boxes side by side in a periodic 32x16x16 domain on two ranks:
+    # they share the x = 16 plane and, through the periodic wrap, x = 0:
+    # 2 x 256 faces, each counted for both ranks
+    boxes = picsynth.uniform_boxes((32, 16, 16), 16)
+    per = oracle.comm_volume((32, 16, 16), boxes, [0, 1], 2)
+    np.testing.assert_array_equal(per, [512.0, 512.0])
+    assert oracle.comm_volume((32, 16, 16), boxes, [0, 0], 2).sum() == 0.0
+    # c1's eight boxes: rank of box b = b: every box has 6 neighbouring faces
+    # of 16^2 cells (two per axis, one of them through the wrap)
+    wl = picsynth.config("c1")
+    per = oracle.comm_volume(wl.n, wl.boxes, np.arange(8), 8, 2.0)
+    np.testing.assert_array_equal(per, np.full(8, 6 * 256 * 2.0))
