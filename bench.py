@@ -243,7 +243,7 @@ def uneven_boxes(steps=5, warmup=2):
     return res
 
 
-def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, name="c4"):
+def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, name="c4", weights=None):
     """Balancing study on the 384x384x768 / 3456-box drifting-slab workload:
     trains the learned model on two runs (seeds 4 and 6, 207,360 samples),
     then scores heuristic, device-timer and learned costs with SFC and
@@ -266,7 +266,7 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     t0 = time.perf_counter()
     loss = ctx.mlp_train(X, y, epochs=30, batch=1024, seed=eval_seed)
     train_s = time.perf_counter() - t0
-    rec = S.collect(ctx, steps, interval, learned=True)
+    rec = S.collect(ctx, steps, interval, learned=True, per_step=True)
     # inference cost on 4096 boxes of features (the mixed-box layout's count)
     Xi = np.ascontiguousarray(np.resize(rec["feat"].reshape(-1, 16), (4096, 16)))
     ctx.mlp_predict(Xi)
@@ -274,10 +274,20 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     for _ in range(20):
         ctx.mlp_predict(Xi)
     infer_us = (time.perf_counter() - t0) / 20 * 1e6
-    E = S.evaluate(rec, wl.boxes, ranks)
+    # heuristic variants: the paper's SFC-favouring weights (0.02 / 0.98) and,
+    # when given, the weights calibrated on this GPU
+    extra = {"heuristic_w0.02": S.heuristic_from_counts(rec, wl.boxes, 0.02, 0.98)}
+    if weights is not None:
+        extra["heuristic_calibrated"] = S.heuristic_from_counts(rec, wl.boxes, *weights)
+    # the model's own predictions at every t_i (whatever the fallback rule
+    # decided) and their cost-weighted error on the interval that follows
+    model = np.stack([np.maximum(np.expm1(ctx.mlp_predict(f).astype(np.float64)), 0.0) for f in rec["feat"]])
+    pred_err = [float(np.abs(model[i] - t).sum() / max(t.sum(), 1e-300)) for i, t in enumerate(rec["timer"])]
+    ctx.finalize()
+    extra["learned_model"] = model
+    E = S.evaluate(rec, wl.boxes, ranks, extra=extra)
     summ = S.summary(E)
     fallbacks = int(sum(1 for u in rec["learned_used"] if u != pb.PIC_COST_LEARNED))
-    ctx.finalize()
     # the balancing loop replayed on the held-out run: no balancing, one
     # static rebalance, and dynamic rebalancing every 10/20/30 steps with
     # 5/10/15% adoption thresholds (timer and learned costs)
@@ -296,14 +306,46 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
                         "E_mean": float(Ev.mean()), "adoptions": a}
     # halo bytes per policy: FP32 E, B and J (9 x 4 bytes) per cross-rank cell face
     comm = S.comm_per_policy(rec, wl.boxes, wl.n, ranks, bytes_per_face_cell=36.0)
-    out = {"E_mean": summ, "loop_replay": loop, "halo_bytes_per_rebalance_mapping": comm, "rebalances": int(len(rec["timer"]) - 1),
+    # interval x threshold sweep on the per-step device-timer records
+    t0 = time.perf_counter()
+    sweep = S.sweep(rec["timer_step"], wl.boxes, ranks)
+    sweep_s = time.perf_counter() - t0
+    out = {"E_mean": summ, "loop_replay": loop, "halo_bytes_per_rebalance_mapping": comm,
+           "interval_threshold_sweep": sweep, "sweep_seconds": sweep_s, "rebalances": int(len(rec["timer"]) - 1),
            "learned_over_timer": {p: summ["learned"][p] / summ["timer"][p] for p in summ["timer"]},
+           "model_over_timer": {p: summ["learned_model"][p] / summ["timer"][p] for p in summ["timer"]},
            "learned_minus_heuristic": {p: summ["learned"][p] - summ["heuristic"][p] for p in summ["timer"]},
-           "learned_fallbacks": fallbacks, "train_samples": int(len(y)), "train_loss_first_last":
+           "learned_fallbacks": fallbacks, "learned_error_per_interval": pred_err, "train_samples": int(len(y)), "train_loss_first_last":
            [float(loss[0]), float(loss[-1])], "train_seconds": train_s, "mlp_predict_4096_us": infer_us,
            "ranks": ranks, "interval": interval, "steps": steps, "wall_s": time.perf_counter() - t_start,
            "workload": "384x384x768, 3456 boxes of 32^3, e-/p+ slab z in [374,394) at 16 ppc each drifting "
                        "u_z=0.05, quadratic, FP32; train seeds 4,6; evaluate seed 5"}
+    return out
+
+
+def box_edge_sweep(edges=(16, 32, 64, 128), steps=300, interval=10, ranks=96, seed=5):
+    """The balancing study's box-size axis: the 384x384x768 drifting-slab run
+    with cubic boxes of each edge, dynamic balancing every `interval` steps
+    at the 10% threshold on device-timer costs, against no balancing."""
+    import picsynth
+    from paper_2104_11385_amd import lb_study as S
+    out = {}
+    for edge in edges:
+        wl = picsynth.config("c4")
+        wl.seed = seed
+        wl.boxes = picsynth.uniform_boxes(wl.n, edge)
+        ctx = ctx_for(wl)
+        t0 = time.perf_counter()
+        rec = S.collect(ctx, steps, interval)
+        run_s = time.perf_counter() - t0
+        ctx.finalize()
+        r = {"boxes": int(len(wl.boxes)), "boxes_per_rank": len(wl.boxes) / ranks, "run_seconds": run_s}
+        for pname, pol in S.POLICIES.items():
+            r[f"{pname}/none"] = float(S.replay(rec, wl.boxes, ranks, pol, mode="none")[0].mean())
+            E, a = S.replay(rec, wl.boxes, ranks, pol, mode="dynamic", every=1, threshold=0.10)
+            r[f"{pname}/dynamic"] = float(E.mean())
+            r[f"{pname}/adoptions"] = a
+        out[str(edge)] = r
     return out
 
 
@@ -319,8 +361,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-lb", action="store_true", help="skip the load-balancing study")
+    ap.add_argument("--no-calibrate", action="store_true", help="skip the heuristic-weight calibration runs")
     ap.add_argument("--no-c3", action="store_true", help="skip the uneven-box (4096 mixed boxes) comparison")
     ap.add_argument("--lb-steps", type=int, default=300)
+    ap.add_argument("--lb-edges", action="store_true", help="also sweep the balancing study's box edge (16..128)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -361,8 +405,17 @@ def main():
     }
     if not args.no_c3:
         out["uneven_boxes"] = uneven_boxes()
+    weights = None
+    if not args.no_calibrate:
+        from paper_2104_11385_amd import calibrate
+        cal = {f"order{o}": calibrate.run(order=o) for o in (2, 3)}
+        cal["grid"] = "256^3, 64 boxes of 64^3, e- at 27 ppc (u_th 0.01) vs no particles, FP32, persistent + graph"
+        out["heuristic_calibration"] = cal
+        weights = (cal["order2"]["w_particle"], cal["order2"]["w_cell"])
     if not args.no_lb:
-        out["lb_study"] = lb_study(steps=args.lb_steps)
+        out["lb_study"] = lb_study(steps=args.lb_steps, weights=weights)
+    if args.lb_edges:
+        out["lb_box_edges"] = box_edge_sweep(steps=args.lb_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -171,10 +171,11 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
  * pic_reset_costs (or pic_init).  LEARNED predicts the next interval's
  * timer cycles from the current box features; it falls back to HEURISTIC
  * when no model is loaded, or when the prediction made at the previous
- * LEARNED call missed the timer costs read since then (the interval it was
- * made for) by more than 15% relative error, sum |pred - t| / sum t over
- * boxes.  Intended order per balancing step: read DEVICE_TIMER, reset,
- * then LEARNED.  *used_strategy (nullable) reports which strategy produced
+ * LEARNED call missed the most recent DEVICE_TIMER reading by more than 15%
+ * relative error, sum |pred - t| / sum t over boxes; that reading should
+ * cover the whole interval the prediction was made for (read the counters
+ * at its end, without a reset inside it).  Intended order per balancing
+ * step: read DEVICE_TIMER, reset, then LEARNED.  *used_strategy (nullable) reports which strategy produced
  * the values. */
 PIC_API int pic_box_costs(pic_ctx *ctx, int32_t strategy, double *costs, int32_t *used_strategy);
 

@@ -102,8 +102,11 @@ bool gpd_supported(const int tile[3], int halo);
 size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo);
 // Field buffers of one Yee update: inputs E, B, J; outputs Eo, Bo; Z is the
 // J buffer cleared for the next deposit.
+// Fields of one Yee update: inputs E, B (overwritten with B^{n+1/2}), J;
+// outputs Eo, Bo; Z is the J buffer cleared for the next deposit.
 struct YeeBuffers {
-    const void *E[3], *B[3], *J[3];
+    const void *E[3], *J[3];
+    void *B[3];
     void *Eo[3], *Bo[3], *Z[3];
 };
 hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);

@@ -118,18 +118,17 @@ __device__ void wave_sum_add(double *arr, int key, double v) {
 }
 
 // Box, tile and cell-in-tile of global cell (x, y, z).
-__device__ __forceinline__ void locate(const Geom &G, int x, int y, int z, int &box, int &tile,
-                                       int &local) {
-    int b = G.coarse_box[(x / G.g[0]) + G.cg[0] * ((y / G.g[1]) + G.cg[1] * (z / G.g[2]))];
-    int lx = x - G.box_lo[3 * b], ly = y - G.box_lo[3 * b + 1], lz = z - G.box_lo[3 * b + 2];
-    int tx = lx / G.T[0], ty = ly / G.T[1], tz = lz / G.T[2];
-    box = b;
-    tile = G.box_tile_off[b] + tx + G.box_nt[3 * b] * (ty + G.box_nt[3 * b + 1] * tz);
-    local = (lx - tx * G.T[0]) + G.T[0] * ((ly - ty * G.T[1]) + G.T[1] * (lz - tz * G.T[2]));
-}
-
 __device__ __forceinline__ int box_of_cell(const Geom &G, int x, int y, int z) {
     return G.coarse_box[(x / G.g[0]) + G.cg[0] * ((y / G.g[1]) + G.cg[1] * (z / G.g[2]))];
+}
+
+// Tile of box b holding the point (x, y, z) of that box, and the point's
+// index inside the tile.
+__device__ __forceinline__ void locate_in_box(const Geom &G, int b, int x, int y, int z, int &tile, int &local) {
+    int lx = x - G.box_lo[3 * b], ly = y - G.box_lo[3 * b + 1], lz = z - G.box_lo[3 * b + 2];
+    int tx = lx / G.T[0], ty = ly / G.T[1], tz = lz / G.T[2];
+    tile = G.box_tile_off[b] + tx + G.box_nt[3 * b] * (ty + G.box_nt[3 * b + 1] * tz);
+    local = (lx - tx * G.T[0]) + G.T[0] * ((ly - ty * G.T[1]) + G.T[1] * (lz - tz * G.T[2]));
 }
 
 // ---------------------------------------------------------------------------
@@ -213,21 +212,23 @@ __global__ void k_load(Particles<real> P, LoadArgs a) {
 // Tile sort.  Output order: by (tile, species), and inside a (tile, species)
 // segment by (rank of the particle within its cell, cell).  Consecutive
 // particles then sit in distinct cells, so the lanes of a wave deposit into
-// distinct LDS addresses.  For quadratic shapes the "cell" is the nearest
-// node, which fixes the start of the particle's deposit window.
+// distinct LDS addresses.  A particle belongs to the box of its cell (that
+// box's timer pays for it, as the box counts say); inside the box, quadratic
+// shapes use the nearest node as the "cell", which fixes the start of the
+// deposit window and centres the tile's halo margin.  A node on the box's
+// upper face falls back to the cell in that dimension.
 // ---------------------------------------------------------------------------
 
 template <typename real>
-__device__ __forceinline__ void sort_cell(const Particles<real> &P, const Geom &G, int p, int &x, int &y,
-                                          int &z) {
+__device__ __forceinline__ void sort_point(const Particles<real> &P, const Geom &G, int p, int &b, int &x, int &y,
+                                           int &z) {
     unpack_cell(P.cell[p], x, y, z);
+    b = box_of_cell(G, x, y, z);
     if (G.order == 2) {
-        x += P.f[0][p] >= (real)0.5;
-        y += P.f[1][p] >= (real)0.5;
-        z += P.f[2][p] >= (real)0.5;
-        if (x == G.n[0]) x = 0;
-        if (y == G.n[1]) y = 0;
-        if (z == G.n[2]) z = 0;
+        const int *lo = G.box_lo + 3 * b, *nt = G.box_nt + 3 * b;
+        x += (P.f[0][p] >= (real)0.5) && (x + 1 < lo[0] + nt[0] * G.T[0]);
+        y += (P.f[1][p] >= (real)0.5) && (y + 1 < lo[1] + nt[1] * G.T[1]);
+        z += (P.f[2][p] >= (real)0.5) && (z + 1 < lo[2] + nt[2] * G.T[2]);
     }
 }
 
@@ -237,8 +238,8 @@ __global__ void k_sort_key(Particles<real> P, int np, Geom G, uint32_t *cellcnt,
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     int x, y, z, b, t, l;
-    sort_cell(P, G, p, x, y, z);
-    locate(G, x, y, z, b, t, l);
+    sort_point(P, G, p, b, x, y, z);
+    locate_in_box(G, b, x, y, z, t, l);
     uint32_t k = (uint32_t)((t * G.nsp + P.sp[p]) * G.Tvol + l);
     key[p] = k;
     rank[p] = atomicAdd(&cellcnt[k], 1u);
@@ -946,25 +947,38 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
         }
         const TileDesc td = A.tiles[tile];
 
-        // stage E and B of the tile window; clear the J window
-        for (int i = tid; i < 6 * C::NEB; i += nthr) {
-            int comp = i / C::NEB;
-            int r = i - comp * C::NEB;
-            int lx = r % C::EX;
-            int r2 = r / C::EX;
-            int ly = r2 % C::EY;
-            int lz = r2 / C::EY;
-            int gx = td.x0 - H - C::RL_EB + lx, gy = td.y0 - H - C::RL_EB + ly, gz = td.z0 - H - C::RL_EB + lz;
-            if (small) {
-                gx = wrap_any(gx, A.n[0]);
-                gy = wrap_any(gy, A.n[1]);
-                gz = wrap_any(gz, A.n[2]);
-            } else {
-                gx = wrap_near(gx, A.n[0]);
-                gy = wrap_near(gy, A.n[1]);
-                gz = wrap_near(gz, A.n[2]);
+        // stage E and B of the tile window (one index computation serves the
+        // six components; windows inside the domain need no wrap); clear the
+        // J window
+        {
+            const int ox = td.x0 - H - C::RL_EB, oy = td.y0 - H - C::RL_EB, oz = td.z0 - H - C::RL_EB;
+            const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::EX <= A.n[0] && oy + C::EY <= A.n[1] &&
+                                oz + C::EZ <= A.n[2];
+            const size_t sy = (size_t)A.n[0], sz = (size_t)A.n[0] * A.n[1];
+            for (int i = tid; i < C::NEB; i += nthr) {
+                int lx = i % C::EX;
+                int r2 = i / C::EX;
+                int ly = r2 % C::EY;
+                int lz = r2 / C::EY;
+                int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+                if (!inside) {
+                    if (small) {
+                        gx = wrap_any(gx, A.n[0]);
+                        gy = wrap_any(gy, A.n[1]);
+                        gz = wrap_any(gz, A.n[2]);
+                    } else {
+                        gx = wrap_near(gx, A.n[0]);
+                        gy = wrap_near(gy, A.n[1]);
+                        gz = wrap_near(gz, A.n[2]);
+                    }
+                }
+                const size_t g = (size_t)gx + sy * gy + sz * gz;
+                real v[6];
+#pragma unroll
+                for (int comp = 0; comp < 6; ++comp) v[comp] = A.EB[comp][g];
+#pragma unroll
+                for (int comp = 0; comp < 6; ++comp) sEB[comp * C::NEB + i] = v[comp];
             }
-            sEB[i] = A.EB[comp][gx + (size_t)A.n[0] * (gy + (size_t)A.n[1] * gz)];
         }
         for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = 0.0;
         if (tid == 0) {
@@ -1000,27 +1014,37 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
         if (nslow) atomicAdd(&sSlow, nslow);
         __syncthreads();
 
-        // flush the J window
-        for (int i = tid; i < 3 * C::NJ; i += nthr) {
-            real v = (real)sJ[i];
-            if (v != (real)0) {
-                int comp = i / C::NJ;
-                int r = i - comp * C::NJ;
-                int lx = r % C::JX;
-                int r2 = r / C::JX;
+        // flush the J window (nonzero entries only)
+        {
+            const int ox = td.x0 - H - C::RL_J, oy = td.y0 - H - C::RL_J, oz = td.z0 - H - C::RL_J;
+            const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::JX <= A.n[0] && oy + C::JY <= A.n[1] &&
+                                oz + C::JZ <= A.n[2];
+            const size_t sy = (size_t)A.n[0], sz = (size_t)A.n[0] * A.n[1];
+            for (int i = tid; i < C::NJ; i += nthr) {
+                real v[3];
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) v[comp] = (real)sJ[comp * C::NJ + i];
+                if (v[0] == (real)0 && v[1] == (real)0 && v[2] == (real)0) continue;
+                int lx = i % C::JX;
+                int r2 = i / C::JX;
                 int ly = r2 % C::JY;
                 int lz = r2 / C::JY;
-                int gx = td.x0 - H - C::RL_J + lx, gy = td.y0 - H - C::RL_J + ly, gz = td.z0 - H - C::RL_J + lz;
-                if (small) {
-                    gx = wrap_any(gx, A.n[0]);
-                    gy = wrap_any(gy, A.n[1]);
-                    gz = wrap_any(gz, A.n[2]);
-                } else {
-                    gx = wrap_near(gx, A.n[0]);
-                    gy = wrap_near(gy, A.n[1]);
-                    gz = wrap_near(gz, A.n[2]);
+                int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+                if (!inside) {
+                    if (small) {
+                        gx = wrap_any(gx, A.n[0]);
+                        gy = wrap_any(gy, A.n[1]);
+                        gz = wrap_any(gz, A.n[2]);
+                    } else {
+                        gx = wrap_near(gx, A.n[0]);
+                        gy = wrap_near(gy, A.n[1]);
+                        gz = wrap_near(gz, A.n[2]);
+                    }
                 }
-                atomic_add_global(&A.J[comp][gx + (size_t)A.n[0] * (gy + (size_t)A.n[1] * gz)], v);
+                const size_t g = (size_t)gx + sy * gy + sz * gz;
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp)
+                    if (v[comp] != (real)0) atomic_add_global(&A.J[comp][g], v[comp]);
             }
         }
         if (tid == 0) {
@@ -1041,6 +1065,141 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
 // other field buffer; the next step's J buffer is cleared on the way.
 // Plane arrays cover in-plane offsets -1 .. T+1 (index + 1).
 // ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
+// Yee update in two streaming passes.  Threads own (x, y) columns and march
+// along z, carrying the z neighbours in registers; x and y neighbours are
+// read through the caches.
+//   pass 1 (in place): B <- B^{n+1/2} = B^n - dt/2 curl E^n
+//   pass 2: E^{n+1} = E^n + dt (curl B^{n+1/2} - J) into the other E buffer,
+//           B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1} into the other B buffer,
+//           and the next step's J buffer cleared.  The E^{n+1} values at the
+//           +x, +y neighbours that the second curl needs are recomputed from
+//           the same inputs; the +z ones are carried to the next plane.
+// Curl of E uses forward differences, curl of B backward ones (Yee cell).
+// ---------------------------------------------------------------------------
+
+constexpr int YSX = 64, YSY = 4, YSZ = 16;
+
+struct Yee2Args {
+    const void *E[3], *J[3];
+    void *B[3];             // B^n in, B^{n+1/2} out (pass 1); B^{n+1/2} in (pass 2)
+    void *Eo[3], *Bo[3], *Z[3];
+    int n[3];
+    double dt;
+};
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_yee_bhalf(Yee2Args a) {
+    const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+    const int x = blockIdx.x * YSX + (threadIdx.x & (YSX - 1));
+    const int y = blockIdx.y * YSY + (threadIdx.x / YSX);
+    if (x >= nx || y >= ny) return;
+    const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
+    const real hdt = (real)(0.5 * a.dt);
+    const real *Ex = (const real *)a.E[0], *Ey = (const real *)a.E[1], *Ez = (const real *)a.E[2];
+    real *Bx = (real *)a.B[0], *By = (real *)a.B[1], *Bz = (real *)a.B[2];
+    const size_t sxy = (size_t)nx * ny;
+    const int xp = x + 1 == nx ? 0 : x + 1, yp = y + 1 == ny ? 0 : y + 1;
+    const size_t col = (size_t)x + (size_t)nx * y, colx = (size_t)xp + (size_t)nx * y,
+                 coly = (size_t)x + (size_t)nx * yp;
+    size_t g = col + sxy * z0;
+    real ex = Ex[g], ey = Ey[g];
+    for (int k = z0; k < z1; ++k) {
+        const size_t gk = sxy * k, gn = sxy * (k + 1 == nz ? 0 : k + 1);
+        const real exn = Ex[col + gn], eyn = Ey[col + gn];
+        const real ez = Ez[col + gk];
+        const real eyx = Ey[colx + gk], ezx = Ez[colx + gk];
+        const real exy = Ex[coly + gk], ezy = Ez[coly + gk];
+        const real cx = (ezy - ez) - (eyn - ey);
+        const real cy = (exn - ex) - (ezx - ez);
+        const real cz = (eyx - ey) - (exy - ex);
+        g = col + gk;
+        Bx[g] = Bx[g] - hdt * cx;
+        By[g] = By[g] - hdt * cy;
+        Bz[g] = Bz[g] - hdt * cz;
+        ex = exn;
+        ey = eyn;
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_yee_eb(Yee2Args a) {
+    const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+    const int x = blockIdx.x * YSX + (threadIdx.x & (YSX - 1));
+    const int y = blockIdx.y * YSY + (threadIdx.x / YSX);
+    if (x >= nx || y >= ny) return;
+    const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
+    const real dt = (real)a.dt, hdt = (real)(0.5 * a.dt);
+    const real *Ex = (const real *)a.E[0], *Ey = (const real *)a.E[1], *Ez = (const real *)a.E[2];
+    const real *Jx = (const real *)a.J[0], *Jy = (const real *)a.J[1], *Jz = (const real *)a.J[2];
+    const real *Hx = (const real *)a.B[0], *Hy = (const real *)a.B[1], *Hz = (const real *)a.B[2];
+    const size_t sxy = (size_t)nx * ny;
+    const int xp = x + 1 == nx ? 0 : x + 1, yp = y + 1 == ny ? 0 : y + 1;
+    const int xm = x == 0 ? nx - 1 : x - 1, ym = y == 0 ? ny - 1 : y - 1;
+    // columns: P, +x, +y, -x, -y, +x-y, -x+y
+    const size_t c0 = (size_t)x + (size_t)nx * y, cxp = (size_t)xp + (size_t)nx * y,
+                 cyp = (size_t)x + (size_t)nx * yp, cxm = (size_t)xm + (size_t)nx * y,
+                 cym = (size_t)x + (size_t)nx * ym, cxpym = (size_t)xp + (size_t)nx * ym,
+                 cxmyp = (size_t)xm + (size_t)nx * yp;
+    // carried from plane k-1: Bh_x, Bh_y at P-z, +x-z (x only), +y-z (y only)
+    const size_t gm = sxy * (z0 == 0 ? nz - 1 : z0 - 1);
+    real hx_m = Hx[c0 + gm], hy_m = Hy[c0 + gm];
+    real hx_xm = Hx[cxp + gm];   // Bh_x(P+x-z)
+    real hy_ym = Hy[cyp + gm];   // Bh_y(P+y-z)
+    // E^{n+1}_x, E^{n+1}_y at P of the first plane (later carried as the +z values)
+    real hx0, hy0, hz0;
+    real e1x, e1y;
+    {
+        const size_t gk = sxy * z0;
+        hx0 = Hx[c0 + gk];
+        hy0 = Hy[c0 + gk];
+        hz0 = Hz[c0 + gk];
+        const real hzym = Hz[cym + gk], hzxm = Hz[cxm + gk];
+        e1x = Ex[c0 + gk] + dt * (((hz0 - hzym) - (hy0 - hy_m)) - Jx[c0 + gk]);
+        e1y = Ey[c0 + gk] + dt * (((hx0 - hx_m) - (hz0 - hzxm)) - Jy[c0 + gk]);
+    }
+    for (int k = z0; k < z1; ++k) {
+        const size_t gk = sxy * k, gn = sxy * (k + 1 == nz ? 0 : k + 1);
+        // Bh on plane k at the columns the curls need
+        const real hyxm = Hy[cxm + gk], hxym = Hx[cym + gk];
+        const real hxx = Hx[cxp + gk], hyx = Hy[cxp + gk], hzx = Hz[cxp + gk];
+        const real hxy = Hx[cyp + gk], hyy = Hy[cyp + gk], hzy = Hz[cyp + gk];
+        const real hxxym = Hx[cxpym + gk], hyxmyp = Hy[cxmyp + gk];
+        // E^{n+1} on plane k: z at P, +x, +y; y at +x; x at +y
+        const real e1z = Ez[c0 + gk] + dt * (((hy0 - hyxm) - (hx0 - hxym)) - Jz[c0 + gk]);
+        const real e1zx = Ez[cxp + gk] + dt * (((hyx - hy0) - (hxx - hxxym)) - Jz[cxp + gk]);
+        const real e1zy = Ez[cyp + gk] + dt * (((hyy - hyxmyp) - (hxy - hx0)) - Jz[cyp + gk]);
+        const real e1yx = Ey[cxp + gk] + dt * (((hxx - hx_xm) - (hzx - hz0)) - Jy[cxp + gk]);
+        const real e1xy = Ex[cyp + gk] + dt * (((hzy - hz0) - (hyy - hy_ym)) - Jx[cyp + gk]);
+        // plane k+1: Bh there and E^{n+1}_x, E^{n+1}_y at P+z
+        const real hxn = Hx[c0 + gn], hyn = Hy[c0 + gn], hzn = Hz[c0 + gn];
+        const real hznym = Hz[cym + gn], hznxm = Hz[cxm + gn];
+        const real e1xn = Ex[c0 + gn] + dt * (((hzn - hznym) - (hyn - hy0)) - Jx[c0 + gn]);
+        const real e1yn = Ey[c0 + gn] + dt * (((hxn - hx0) - (hzn - hznxm)) - Jy[c0 + gn]);
+        // outputs at P
+        const size_t g = c0 + gk;
+        ((real *)a.Eo[0])[g] = e1x;
+        ((real *)a.Eo[1])[g] = e1y;
+        ((real *)a.Eo[2])[g] = e1z;
+        ((real *)a.Bo[0])[g] = hx0 - hdt * ((e1zy - e1z) - (e1yn - e1y));
+        ((real *)a.Bo[1])[g] = hy0 - hdt * ((e1xn - e1x) - (e1zx - e1z));
+        ((real *)a.Bo[2])[g] = hz0 - hdt * ((e1yx - e1y) - (e1xy - e1x));
+        ((real *)a.Z[0])[g] = (real)0;
+        ((real *)a.Z[1])[g] = (real)0;
+        ((real *)a.Z[2])[g] = (real)0;
+        // carry to plane k+1
+        hx_m = hx0;
+        hy_m = hy0;
+        hx_xm = hxx;
+        hy_ym = hyy;
+        hx0 = hxn;
+        hy0 = hyn;
+        hz0 = hzn;
+        e1x = e1xn;
+        e1y = e1yn;
+    }
+}
 
 constexpr int YTX = 32, YTY = 8, YPX = YTX + 3, YPY = YTY + 3, YPN = YPX * YPY;
 
@@ -1447,7 +1606,37 @@ hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st) {
     return order == 2 ? gpd_tile<float, 2>(L, st) : gpd_tile<float, 1>(L, st);
 }
 
+static hipError_t launch_yee_fused(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
+
+// The two-pass update writes B^{n+1/2} over the current B buffer, which the
+// step no longer needs once the new fields are in the other buffers.
 hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
+#ifdef PB_YEE_FUSED
+    return launch_yee_fused(prec, Y, n, dt, st);
+#endif
+    Yee2Args a;
+    for (int c = 0; c < 3; ++c) {
+        a.E[c] = Y.E[c];
+        a.B[c] = Y.B[c];
+        a.J[c] = Y.J[c];
+        a.Eo[c] = Y.Eo[c];
+        a.Bo[c] = Y.Bo[c];
+        a.Z[c] = Y.Z[c];
+        a.n[c] = n[c];
+    }
+    a.dt = dt;
+    dim3 grd((n[0] + YSX - 1) / YSX, (n[1] + YSY - 1) / YSY, (n[2] + YSZ - 1) / YSZ);
+    if (prec == 8) {
+        k_yee_bhalf<double><<<grd, 256, 0, st>>>(a);
+        k_yee_eb<double><<<grd, 256, 0, st>>>(a);
+    } else {
+        k_yee_bhalf<float><<<grd, 256, 0, st>>>(a);
+        k_yee_eb<float><<<grd, 256, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_yee_fused(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
     YeeArgs a;
     for (int c = 0; c < 3; ++c) {
         a.E[c] = Y.E[c];

@@ -829,7 +829,7 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
     StateBackup bk;
     int rc = copy_state(ctx, bk, true);
     if (rc) return rc;
-    int saved_since_sort = ctx->steps_since_sort, saved_jcur = ctx->jcur;
+    int saved_jcur = ctx->jcur;
     int64_t saved_step = ctx->step_no;
     bool saved_graph = ctx->use_graph, saved_timing = ctx->timing;
     ctx->use_graph = false;
@@ -837,10 +837,11 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
         return ctx->fail(PIC_EDEVICE, "autotune: hipEventCreate");
+    // the field buffers to restore are those of the saved step's parity
     auto trial = [&](const pic_tuning &t, double &ms) -> int {
+        ctx->jcur = saved_jcur;
         int r = copy_state(ctx, bk, false);
         if (r) return r;
-        ctx->jcur = saved_jcur;
         r = pic_set_tuning(ctx, &t);
         if (r) return r;
         if ((r = ctx->step(1))) return r;
@@ -882,10 +883,9 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc) return rc;
-    if ((rc = copy_state(ctx, bk, false))) return rc;
     ctx->jcur = saved_jcur;
+    if ((rc = copy_state(ctx, bk, false))) return rc;
     if ((rc = pic_set_tuning(ctx, &win))) return rc;
-    ctx->steps_since_sort = std::min(saved_since_sort, 0);
     ctx->step_no = saved_step;
     ctx->use_graph = saved_graph;
     ctx->timing = saved_timing;

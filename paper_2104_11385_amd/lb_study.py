@@ -28,10 +28,13 @@ STRATS = ("heuristic", "timer", "learned")
 POLICIES = {"sfc": pb.LB_SFC, "knapsack": pb.LB_KNAPSACK}
 
 
-def collect(ctx, steps: int, interval: int, learned: bool = False):
-    """Runs `steps` steps, recording costs every `interval` steps."""
+def collect(ctx, steps: int, interval: int, learned: bool = False, per_step: bool = False):
+    """Runs `steps` steps, recording costs every `interval` steps.  With
+    `per_step` the device-timer cycles are also read after every step
+    (`timer_step`, one row per step; the interval rows are their sums)."""
     nint = steps // interval
-    rec = {"heuristic": [], "feat": [], "timer": [], "learned": [], "learned_used": [], "counts": []}
+    rec = {"heuristic": [], "feat": [], "timer": [], "learned": [], "learned_used": [], "counts": [],
+           "timer_step": []}
     ctx.reset_costs()
     for i in range(nint + 1):
         h, _ = ctx.box_costs(pb.PIC_COST_HEURISTIC)
@@ -45,6 +48,18 @@ def collect(ctx, steps: int, interval: int, learned: bool = False):
         if i == nint:
             break
         ctx.reset_costs()
+        if per_step:
+            # the counters keep running over the interval, so the library's
+            # last timer reading (which its learned-cost fallback compares
+            # with) is still the whole interval's; steps are differences
+            prev = 0.0
+            for _ in range(interval):
+                ctx.step(1)
+                t, _ = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
+                rec["timer_step"].append(t - prev)
+                prev = t
+            rec["timer"].append(prev)
+            continue
         ctx.step(interval)
         t, _ = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
         rec["timer"].append(t)
@@ -61,12 +76,22 @@ def training_set(recs):
     return np.concatenate(X).astype(np.float32), np.concatenate(y).astype(np.float32)
 
 
-def evaluate(rec, boxes, n_ranks: int, predictions=None):
+def heuristic_from_counts(rec, boxes, w_particle: float, w_cell: float):
+    """Heuristic costs w_p * N + w_c * cells at every t_i from the recorded
+    particle counts (for weights other than the run's own)."""
+    b = np.asarray(boxes, dtype=np.int64)
+    cells = ((b[:, 3] - b[:, 0]) * (b[:, 4] - b[:, 1]) * (b[:, 5] - b[:, 2])).astype(float)
+    return w_particle * np.asarray(rec["counts"], dtype=float) + w_cell * cells[None, :]
+
+
+def evaluate(rec, boxes, n_ranks: int, predictions=None, extra=None):
     """Efficiency of each (strategy, policy) per load-balancing step.
 
     Decision at t_i (i >= 1) governs interval i, judged by timer[i]:
-    heuristic and learned use the state at t_i, the timer uses timer[i-1]."""
-    out = {s: {p: [] for p in POLICIES} for s in STRATS}
+    heuristic and learned use the state at t_i, the timer uses timer[i-1].
+    `extra` maps further strategy names to costs at every t_i."""
+    extra = extra or {}
+    out = {s: {p: [] for p in POLICIES} for s in (*STRATS, *extra)}
     nint = len(rec["timer"])
     for i in range(1, nint):
         judge = rec["timer"][i]
@@ -75,6 +100,8 @@ def evaluate(rec, boxes, n_ranks: int, predictions=None):
             costs["learned"] = predictions[i]
         elif len(rec["learned"]):
             costs["learned"] = rec["learned"][i]
+        for name, c in extra.items():
+            costs[name] = c[i]
         for s, c in costs.items():
             for pname, pol in POLICIES.items():
                 rank, _ = pb.lb_distribute(np.maximum(c, 0.0), boxes, n_ranks, pol)
@@ -114,7 +141,11 @@ def replay(rec, boxes, n_ranks: int, policy: int, strategy="timer", mode="dynami
     E, adopted = [], 0
     for i in range(nint):
         if i >= 1 and mode != "none" and (mode == "dynamic" and i % every == 0 or mode == "static" and i == 1):
-            c = np.maximum(rec["timer"][i - 1] if strategy == "timer" else rec[strategy][i], 0.0)
+            if strategy == "timer":
+                c = np.sum(rec["timer"][max(0, i - every) if mode == "dynamic" else 0:i], axis=0)
+            else:
+                c = rec[strategy][i]
+            c = np.maximum(c, 0.0)
             proposed, e_new = pb.lb_distribute(c, boxes, n_ranks, policy)
             e_cur = pb.lb_efficiency(c, mapping, n_ranks)
             if mode == "static" or pb.lb_should_adopt(e_cur, e_new, threshold):
@@ -122,6 +153,24 @@ def replay(rec, boxes, n_ranks: int, policy: int, strategy="timer", mode="dynami
                 adopted += 1
         E.append(pb.lb_efficiency(rec["timer"][i], mapping, n_ranks))
     return np.array(E), adopted
+
+
+def sweep(timer_step, boxes, n_ranks: int, intervals=(1, 3, 10, 30, 100, 300), thresholds=(0.05, 0.10, 0.15)):
+    """Mean step efficiency of dynamic balancing on per-step timer records,
+    for each policy, balancing interval (steps) and adoption threshold, next
+    to no balancing (Sec. 3.3's parameter study, on virtual ranks)."""
+    rec = {"timer": np.asarray(timer_step, dtype=float)}
+    T = len(rec["timer"])
+    out = {}
+    for pname, pol in POLICIES.items():
+        out[f"{pname}/none"] = float(replay(rec, boxes, n_ranks, pol, mode="none")[0].mean())
+        for k in intervals:
+            if k >= T:
+                continue
+            for thr in thresholds:
+                E, a = replay(rec, boxes, n_ranks, pol, mode="dynamic", every=k, threshold=thr)
+                out[f"{pname}/every{k}/thr{int(round(thr * 100))}"] = {"E_mean": float(E.mean()), "adoptions": a}
+    return out
 
 
 def summary(E):

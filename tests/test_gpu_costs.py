@@ -84,6 +84,41 @@ def test_learned_costs_balance_within_3_percent_of_timer():
         for p in ("sfc", "knapsack"):
             assert 0.0 < E[s][p] <= 1.0
     assert out["train_loss_first_last"][1] < out["train_loss_first_last"][0]
+    print("study:", out["E_mean"], "fallbacks", out["learned_fallbacks"], "model error per interval",
+          out["learned_error_per_interval"], "train loss", out["train_loss_first_last"], flush=True)
     for p in ("sfc", "knapsack"):
         assert out["learned_over_timer"][p] >= 0.97, out
-    print("study:", out["E_mean"], "fallbacks", out["learned_fallbacks"])
+
+
+def test_empty_domain_steps_and_costs_nothing():
+    # no particles at all: the sort, the queue and the persistent kernel see
+    # zero work; fields that start at zero stay exactly zero
+    from paper_2104_11385_amd import picbal as pb
+    n = (32, 32, 32)
+    boxes = picsynth.uniform_boxes(n, 16)
+    print("empty domain: 32^3, 8 boxes, no particles", flush=True)
+    ctx = pb.pic_init(n, boxes, [pb.Species(-1.0, 1.0, 0.1, load_mode=0)], 0.5, 2, pb.PIC_FP32, 1)
+    try:
+        for mode, graph in ((pb.PIC_LAUNCH_PERSISTENT, True), (pb.PIC_LAUNCH_BATCHED, False),
+                            (pb.PIC_LAUNCH_PER_BOX, False)):
+            ctx.set_launch_mode(mode, graph)
+            ctx.reset_costs()
+            ctx.step(3)
+            ctx.sync()
+            t, _ = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
+            assert (t == 0).all()
+        assert (ctx.box_counts() == 0).all()
+        for k in range(9):
+            assert not ctx.get_field(k).any()
+        h, _ = ctx.box_costs(pb.PIC_COST_HEURISTIC)
+        np.testing.assert_allclose(h, 0.25 * 16 ** 3)
+    finally:
+        ctx.finalize()
+
+
+def test_heuristic_weight_calibration_small():
+    from paper_2104_11385_amd import calibrate
+    print("calibration: 64^3, boxes of 32^3, 27 ppc vs empty", flush=True)
+    r = calibrate.run(n=(64, 64, 64), box_edge=32, ppc=27, order=2, steps=10, warmup=3)
+    assert 0.0 < r["w_particle"] < 1.0 and abs(r["w_particle"] + r["w_cell"] - 1.0) < 1e-12
+    assert r["ms_step_full"] > r["ms_step_empty"]

@@ -77,3 +77,43 @@ def test_replay_modes():
     # a 100% threshold never adopts
     Ek, ak = S.replay(rec, boxes, 2, pb.LB_KNAPSACK, mode="dynamic", threshold=1.0)
     assert ak == 0 and np.allclose(Ek, En)
+
+
+def test_replay_sums_timer_since_last_balance():
+    boxes = picsynth.uniform_boxes((64, 16, 16), 16)
+    # per-step cycles: box 0 is heavy on even steps, box 3 on odd steps; the
+    # two-step sums are uniform, so every-2 balancing sees no imbalance
+    timer = [[5, 1, 1, 1], [1, 1, 1, 5]] * 3
+    rec = _rec(timer, [[0] * 4] * 7)
+    E2, a2 = S.replay(rec, boxes, 2, pb.LB_KNAPSACK, mode="dynamic", every=2, threshold=0.01)
+    assert a2 == 0
+    # every-1 balancing chases last step's heavy box and always lands wrong
+    E1, a1 = S.replay(rec, boxes, 2, pb.LB_KNAPSACK, mode="dynamic", every=1, threshold=0.01)
+    assert a1 >= 1
+    assert E1[1:].mean() < E2[1:].mean()
+
+
+def test_sweep_keys_and_bounds():
+    boxes = picsynth.uniform_boxes((64, 64, 16), 16)
+    rng = np.random.default_rng(2)
+    ts = rng.uniform(1, 3, (12, len(boxes)))
+    out = S.sweep(ts, boxes, 3, intervals=(1, 3, 30), thresholds=(0.05, 0.15))
+    assert set(out) == {"sfc/none", "knapsack/none", "sfc/every1/thr5", "sfc/every1/thr15", "sfc/every3/thr5",
+                        "sfc/every3/thr15", "knapsack/every1/thr5", "knapsack/every1/thr15",
+                        "knapsack/every3/thr5", "knapsack/every3/thr15"}
+    for k, v in out.items():
+        e = v if isinstance(v, float) else v["E_mean"]
+        assert 0 < e <= 1
+
+
+def test_heuristic_from_counts_and_extra_strategy():
+    boxes = picsynth.uniform_boxes((64, 16, 16), 16)
+    timer = [[8, 1, 1, 1], [1, 1, 1, 8]]
+    rec = _rec(timer, [[0] * 4] * 3)
+    rec["counts"] = np.array([[10, 0, 0, 0], [0, 0, 0, 10], [0, 0, 0, 10]], dtype=float)
+    h = S.heuristic_from_counts(rec, boxes, 0.5, 0.001)
+    np.testing.assert_allclose(h[0], [5 + 4.096, 4.096, 4.096, 4.096])
+    E = S.evaluate(rec, boxes, 2, extra={"mine": h})
+    assert {k for k, v in E.items() if v} == {"heuristic", "timer", "mine"}
+    # the extra strategy sees the load on box 3 at t_1: {3} | {0,1,2}
+    np.testing.assert_allclose(E["mine"]["knapsack"], [5.5 / 8])
