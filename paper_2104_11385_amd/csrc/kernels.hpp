@@ -99,7 +99,7 @@ hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st);
 hipError_t launch_fill_f64(double *a, size_t n, hipStream_t st);
 hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st);
 bool gpd_supported(const int tile[3], int halo);
-size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo);
+size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo, int block);
 // Field buffers of one Yee update: inputs E, B, J; outputs Eo, Bo; Z is the
 // J buffer cleared for the next deposit.
 // Fields of one Yee update: inputs E, B (overwritten with B^{n+1/2}), J;

@@ -439,6 +439,8 @@ struct Cfg {
     // J is accumulated in double: gfx950's LDS atomic add is fast for f64
     // (and integers) but an order of magnitude slower for f32.
     static constexpr size_t lds = (size_t)(6 * NEB) * sizeof(real) + (size_t)(3 * NJ) * sizeof(double);
+    // per-thread slot of the deferred-deposit queue: d0[3], D[3], coef, rel
+    static constexpr size_t qslot = 7 * sizeof(real) + sizeof(int);
 };
 
 // Shape factors of one dimension.  Inputs: d = offset from the reference
@@ -590,7 +592,53 @@ struct DepW {
             moved = k != 0;
         }
     }
+    // The particle keeps its reference (cell or node): window of M+1 nodes
+    // from offset s, differences from the displacement (no cancellation).
+    __device__ __forceinline__ void set_kept(real d0, real D) {
+        real d1 = d0 + D;
+        if (M == 3) {
+            const real sixth = (real)(1.0 / 6.0), tt = (real)(2.0 / 3.0), h = (real)0.5;
+            real u = (real)1 - d0;
+            S0[0] = sixth * u * u * u;
+            S0[1] = tt - d0 * d0 + h * d0 * d0 * d0;
+            S0[2] = tt - u * u + h * u * u * u;
+            S0[3] = sixth * d0 * d0 * d0;
+            real g0 = (real)1 - d0, g1 = (real)1 - d1;
+            real qf = d0 * d0 + d0 * d1 + d1 * d1, qg = g0 * g0 + g0 * g1 + g1 * g1;
+            dS[0] = -D * sixth * qg;
+            dS[1] = -D * (d0 + d1) + h * D * qf;
+            dS[2] = D * (g0 + g1) - h * D * qg;
+            dS[3] = D * sixth * qf;
+            s = -1;
+        } else if (M == 1) {
+            S0[0] = (real)1 - d0;
+            S0[1] = d0;
+            dS[0] = -D;
+            dS[1] = D;
+            s = 0;
+        } else {
+            const real h = (real)0.5;
+            S0[0] = h * (h - d0) * (h - d0);
+            S0[1] = (real)0.75 - d0 * d0;
+            S0[2] = h * (h + d0) * (h + d0);
+            real sg = d0 + d1;
+            dS[0] = -h * D * ((real)1 - sg);
+            dS[1] = -D * sg;
+            dS[2] = h * D * ((real)1 + sg);
+            s = -1;
+        }
+        moved = false;
+    }
 };
+
+// Whether a displacement D from reference offset d0 leaves the reference
+// cell (orders 1, 3: d0 in [0, 1)) or node (order 2: d0 in [-1/2, 1/2)).
+template <typename real, int M>
+__device__ __forceinline__ bool leaves_ref(real d0, real D) {
+    real d1 = d0 + D;
+    if (M == 2) return d1 >= (real)0.5 || d1 < (real)-0.5;
+    return d1 >= (real)1 || d1 < (real)0;
+}
 
 // Interpolates the six field components from an accessor F(comp, i, j, k)
 // where (i,j,k) are offsets from the particle's reference.
@@ -767,10 +815,20 @@ struct PState {
     }
 };
 
+// A particle that changed its reference node inside the staged window: its
+// wider deposit waits in the wave's queue so that it runs with the other
+// queued particles on full waves rather than on otherwise idle lanes.
+template <typename real>
+struct Deferred {
+    bool want;
+    int rel;          // packed window-relative reference node, +8 per byte
+    real d0[3], D[3], coef;
+};
+
 template <typename real, int M, int TX, int TY, int TZ, int H>
 __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, const PState<real> &ps,
                                               const TileDesc &td, real hq, real cq, const real *sEB, double *sJ,
-                                              unsigned &nslow) {
+                                              unsigned &nslow, Deferred<real> &df) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
     int c[3];
     unpack_cell(ps.cell, c[0], c[1], c[2]);
@@ -841,16 +899,30 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
     real D[3] = {A.dt * u[0] * gi, A.dt * u[1] * gi, A.dt * u[2] * gi};
 
     // Esirkepov deposit
-    DepW<real, M> DW[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) DW[d].set(d0[d], D[d]);
     real coef = cq * w;
-    bool moved = DW[0].moved || DW[1].moved || DW[2].moved;
+    bool moved = leaves_ref<real, M>(d0[0], D[0]) || leaves_ref<real, M>(d0[1], D[1]) ||
+                 leaves_ref<real, M>(d0[2], D[2]);
     if (fast) {
-        LdsJ<real, C> acc{sJ, (rel[0] + H + C::RL_J) + C::JX * ((rel[1] + H + C::RL_J) + C::JY * (rel[2] + H + C::RL_J)), 0};
-        if (moved) deposit3<real, M, M + 2>(acc, DW, coef);
-        else deposit3<real, M, M + 1>(acc, DW, coef);
+        if (moved) {
+            df.want = true;
+            df.rel = (rel[0] + 8) | ((rel[1] + 8) << 8) | ((rel[2] + 8) << 16);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                df.d0[d] = d0[d];
+                df.D[d] = D[d];
+            }
+            df.coef = coef;
+        } else {
+            DepW<real, M> DW[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) DW[d].set_kept(d0[d], D[d]);
+            LdsJ<real, C> acc{sJ, (rel[0] + H + C::RL_J) + C::JX * ((rel[1] + H + C::RL_J) + C::JY * (rel[2] + H + C::RL_J)), 0};
+            deposit3<real, M, M + 1>(acc, DW, coef);
+        }
     } else {
+        DepW<real, M> DW[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) DW[d].set(d0[d], D[d]);
         GlobJ<real> acc;
         acc.J = A.J;
 #pragma unroll
@@ -891,15 +963,41 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
     }
 }
 
+// Deposits queue entry s (word k of slot s lives at q[k * stride + s]).
+template <typename real, int M, int TX, int TY, int TZ, int H>
+__device__ __forceinline__ void deposit_queued(const real *qr, const int *qi, int stride, int s, double *sJ) {
+    using C = Cfg<real, M, TX, TY, TZ, H>;
+    {
+        const int pk = qi[s];
+        const int r0 = (pk & 255) - 8, r1 = ((pk >> 8) & 255) - 8, r2 = ((pk >> 16) & 255) - 8;
+        DepW<real, M> DW[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) DW[d].set(qr[d * stride + s], qr[(3 + d) * stride + s]);
+        const real coef = qr[6 * stride + s];
+        LdsJ<real, C> acc{sJ, (r0 + H + C::RL_J) + C::JX * ((r1 + H + C::RL_J) + C::JY * (r2 + H + C::RL_J)), 0};
+        deposit3<real, M, M + 2>(acc, DW, coef);
+    }
+}
+
+// Deposits the first n entries of a wave's queue, one per lane.
+template <typename real, int M, int TX, int TY, int TZ, int H>
+__device__ __forceinline__ void drain_queue(const real *qr, const int *qi, int stride, int slot0, int n, int lane,
+                                            double *sJ) {
+    if (lane < n) deposit_queued<real, M, TX, TY, TZ, H>(qr, qi, stride, slot0 + lane, sJ);
+}
+
 template <typename real, int M, int TX, int TY, int TZ, int H>
 __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real *sEB = reinterpret_cast<real *>(smem_raw);
     double *sJ = reinterpret_cast<double *>(smem_raw + (size_t)6 * C::NEB * sizeof(real));
+    real *qr = reinterpret_cast<real *>(smem_raw + C::lds);           // [7][blockDim.x]
+    int *qi = reinterpret_cast<int *>(qr + 7 * blockDim.x);          // [blockDim.x]
     __shared__ unsigned long long sCyc, sRtc;
     __shared__ unsigned int sSlow;
     __shared__ int sItem[3];
+    __shared__ int sQn[8];  // queue lengths of the block's waves at the end of an item
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nsp = A.nsp;
     const int home = blockIdx.x % kSubQueues;  // blocks are dealt round-robin over the XCDs
@@ -990,21 +1088,55 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
 
         unsigned long long c0 = clock64(), r0 = wall_clock64();
         unsigned nslow = 0;
+        const int lane = tid & 63, qslot0 = tid & ~63;
+        int qn = 0;  // entries in this wave's queue (wave-uniform)
         for (int s = 0; s < nsp; ++s) {
             if (A.mode == MODE_PER_BOX && s != A.species_only) continue;
             int sb = max(pbeg, A.segstart[tile * nsp + s]);
             int se = min(pend, A.segstart[tile * nsp + s + 1]);
             real hq = A.h[s], cq = A.coefq[s];
-            // the next particle's loads are issued before this one is computed
-            int p = sb + tid;
+            // the next particle's loads are issued before this one is computed;
+            // the trip count is the same for every lane of the block
             PState<real> cur;
-            if (p < se) cur.load(A.P, p);
-            for (; p < se; p += nthr) {
+            if (sb + tid < se) cur.load(A.P, sb + tid);
+            for (int base = sb; base < se; base += nthr) {
+                const int p = base + tid;
                 PState<real> nxt;
                 if (p + nthr < se) nxt.load(A.P, p + nthr);
-                push_particle<real, M, TX, TY, TZ, H>(A, p, cur, td, hq, cq, sEB, sJ, nslow);
+                Deferred<real> df;
+                df.want = false;
+                if (p < se) push_particle<real, M, TX, TY, TZ, H>(A, p, cur, td, hq, cq, sEB, sJ, nslow, df);
+                const unsigned long long mask = __ballot(df.want);
+                if (mask) {
+                    const int cnt = __popcll(mask);
+                    if (qn + cnt > 64) {
+                        drain_queue<real, M, TX, TY, TZ, H>(qr, qi, nthr, qslot0, qn, lane, sJ);
+                        qn = 0;
+                    }
+                    if (df.want) {
+                        const int s2 = qslot0 + qn + __popcll(mask & ((1ull << lane) - 1ull));
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            qr[d * nthr + s2] = df.d0[d];
+                            qr[(3 + d) * nthr + s2] = df.D[d];
+                        }
+                        qr[6 * nthr + s2] = df.coef;
+                        qi[s2] = df.rel;
+                    }
+                    qn += cnt;
+                }
                 cur = nxt;
             }
+        }
+        // the entries left in the waves' queues are deposited by the block
+        // together, one per thread, instead of by each wave on its own
+        if (lane == 0) sQn[tid >> 6] = qn;
+        __syncthreads();
+        {
+            const int nw = nthr >> 6;
+            int e = tid, w = 0;
+            while (w < nw && e >= sQn[w]) e -= sQn[w++];
+            if (w < nw) deposit_queued<real, M, TX, TY, TZ, H>(qr, qi, nthr, w * 64 + e, sJ);
         }
         unsigned long long c1 = clock64(), r1 = wall_clock64();
         if ((tid & 63) == 0) {
@@ -1079,7 +1211,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
 // Curl of E uses forward differences, curl of B backward ones (Yee cell).
 // ---------------------------------------------------------------------------
 
-constexpr int YSX = 64, YSY = 4, YSZ = 16;
+constexpr int YSX = 64, YSY = 4, YSZ = 8;
 
 struct Yee2Args {
     const void *E[3], *J[3];
@@ -1538,10 +1670,12 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
     auto kern = k_gpd<real, M, TX, TY, TZ, H>;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::lds);
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(C::lds + 512 * C::qslot));
         if (e != hipSuccess) return e;
         attr = true;
     }
+    if (L.block != 256 && L.block != 512) return hipErrorInvalidValue;
     GpdArgs<real> A;
     A.P = cast<real>(L.P);
     A.segstart = L.segstart;
@@ -1566,7 +1700,7 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
     A.queue_bounds = L.queue_bounds;
     A.queue_head = L.queue_head;
     if (L.grid == 0) return hipSuccess;
-    kern<<<L.grid, L.block, C::lds, st>>>(A);
+    kern<<<L.grid, L.block, C::lds + (size_t)L.block * C::qslot, st>>>(A);
     return hipGetLastError();
 }
 
@@ -1587,14 +1721,14 @@ bool gpd_supported(const int tile[3], int halo) {
            (tile[0] == 8 && tile[1] == 4 && tile[2] == 4) || (tile[0] == 4 && tile[1] == 4 && tile[2] == 4);
 }
 
-size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo) {
+size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo, int block) {
     int rl_eb = order == 1 ? 1 : 2, rh_eb = order == 3 ? 2 : 1, rl_j = order == 1 ? 1 : 2, rh_j = order == 3 ? 3 : 2;
     size_t neb = 1, nj = 1;
     for (int d = 0; d < 3; ++d) {
         neb *= (size_t)(tile[d] + 2 * halo + rl_eb + rh_eb);
         nj *= (size_t)(tile[d] + 2 * halo + rl_j + rh_j);
     }
-    return 6 * neb * (size_t)prec + 3 * nj * sizeof(double);
+    return 6 * neb * (size_t)prec + 3 * nj * sizeof(double) + (size_t)block * (7 * (size_t)prec + sizeof(int));
 }
 
 hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st) {

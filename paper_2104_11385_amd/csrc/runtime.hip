@@ -535,19 +535,21 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     c->tun.sort_interval = 20;
     c->tun.blocks_per_cu = 2;
     const int cand[4][3] = {{8, 4, 4}, {4, 4, 4}, {8, 8, 4}, {8, 8, 8}};
+    // first choice: two blocks per CU fit the LDS; else any tile that fits
     bool chosen = false;
-    for (auto &t : cand) {
-        bool ok = true;
-        for (int b = 0; b < n_boxes && ok; ++b)
-            for (int d = 0; d < 3; ++d)
-                if ((boxes[b].hi[d] - boxes[b].lo[d]) % t[d]) ok = false;
-        if (!ok) continue;
-        if (gpd_lds_bytes(c->prec, c->order, t, 1) > 80 * 1024) continue;  // two blocks per CU
-        std::memcpy(c->tun.tile, t, sizeof(int) * 3);
-        chosen = true;
-        break;
+    for (size_t limit : {(size_t)80 * 1024, (size_t)160 * 1024}) {
+        for (auto &t : cand) {
+            if (chosen) break;
+            bool ok = true;
+            for (int b = 0; b < n_boxes && ok; ++b)
+                for (int d = 0; d < 3; ++d)
+                    if ((boxes[b].hi[d] - boxes[b].lo[d]) % t[d]) ok = false;
+            if (!ok || gpd_lds_bytes(c->prec, c->order, t, 1, 256) > limit) continue;
+            std::memcpy(c->tun.tile, t, sizeof(int) * 3);
+            chosen = true;
+        }
     }
-    if (!chosen) return init_fail(c, PIC_EUNSUPPORTED, "box edges must be multiples of 4");
+    if (!chosen) return init_fail(c, PIC_EUNSUPPORTED, "no compiled tile divides every box edge and fits the LDS");
 
     int rc;
     size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
@@ -712,7 +714,7 @@ PIC_API int pic_set_tuning(pic_ctx *ctx, const pic_tuning *t) {
     if (t->chunk < 64 || t->sort_interval < 1 || t->blocks_per_cu < 1 || t->blocks_per_cu > 16)
         return ctx->fail(PIC_EINVAL, "chunk >= 64, sort_interval >= 1, 1 <= blocks_per_cu <= 16");
     if (!gpd_supported(t->tile, t->halo)) return ctx->fail(PIC_EUNSUPPORTED, "tile shape not compiled");
-    if (gpd_lds_bytes(ctx->prec, ctx->order, t->tile, t->halo) > 160 * 1024)
+    if (gpd_lds_bytes(ctx->prec, ctx->order, t->tile, t->halo, t->block) > 160 * 1024)
         return ctx->fail(PIC_EUNSUPPORTED, "tile needs more LDS than a CU has");
     for (int b = 0; b < ctx->nb; ++b)
         for (int d = 0; d < 3; ++d)
@@ -813,12 +815,13 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
     const int tiles[4][3] = {{8, 4, 4}, {4, 4, 4}, {8, 8, 4}, {8, 8, 8}};
     pic_tuning base = ctx->tun;
     for (auto &t : tiles) {
-        bool ok = gpd_lds_bytes(ctx->prec, ctx->order, t, 1) <= 160 * 1024;
+        bool ok = true;
         for (int b = 0; b < ctx->nb && ok; ++b)
             for (int d = 0; d < 3; ++d)
                 if ((ctx->boxes[b].hi[d] - ctx->boxes[b].lo[d]) % t[d]) ok = false;
         if (!ok) continue;
         for (int blk : {256, 512}) {
+            if (gpd_lds_bytes(ctx->prec, ctx->order, t, 1, blk) > 160 * 1024) continue;
             pic_tuning c = base;
             std::memcpy(c.tile, t, sizeof(int) * 3);
             c.block = blk;
