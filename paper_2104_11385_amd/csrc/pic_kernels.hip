@@ -1189,31 +1189,19 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
 }
 
 // ---------------------------------------------------------------------------
-// Yee update, one pass: B^{n+1/2} = B^n - dt/2 curl E^n; E^{n+1} = E^n +
-// dt (curl B^{n+1/2} - J); B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}.
-// A block owns an x-y tile and marches along z with ring buffers of planes in
-// LDS: E^n (two planes), B^{n+1/2} (two), E^{n+1} (two), plus B^n and J of
-// the current plane.  Inputs are read once and outputs written once into the
-// other field buffer; the next step's J buffer is cleared on the way.
-// Plane arrays cover in-plane offsets -1 .. T+1 (index + 1).
-// ---------------------------------------------------------------------------
-
-// ---------------------------------------------------------------------------
-// Yee update in two streaming passes.  Threads own (x, y) columns and march
+// Yee update in three streaming passes.  Threads own (x, y) columns and march
 // along z, carrying the z neighbours in registers; x and y neighbours are
 // read through the caches.
 //   pass 1 (in place): B <- B^{n+1/2} = B^n - dt/2 curl E^n
 //   pass 2: E^{n+1} = E^n + dt (curl B^{n+1/2} - J) into the other E buffer,
-//           B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1} into the other B buffer,
-//           and the next step's J buffer cleared.  The E^{n+1} values at the
-//           +x, +y neighbours that the second curl needs are recomputed from
-//           the same inputs; the +z ones are carried to the next plane.
+//           and the next step's J buffer cleared
+//   pass 3: B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1} into the other B buffer
 // Curl of E uses forward differences, curl of B backward ones (Yee cell).
 // ---------------------------------------------------------------------------
 
-constexpr int YSX = 64, YSY = 4, YSZ = 8;
+constexpr int YSX = 64, YSY = 4, YSZ = 4;
 
-struct Yee2Args {
+struct YeeArgs {
     const void *E[3], *J[3];
     void *B[3];             // B^n in, B^{n+1/2} out (pass 1); B^{n+1/2} in (pass 2)
     void *Eo[3], *Bo[3], *Z[3];
@@ -1222,7 +1210,7 @@ struct Yee2Args {
 };
 
 template <typename real>
-__global__ __launch_bounds__(256) void k_yee_bhalf(Yee2Args a) {
+__global__ __launch_bounds__(256) void k_yee_bhalf(YeeArgs a) {
     const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
     const int x = blockIdx.x * YSX + (threadIdx.x & (YSX - 1));
     const int y = blockIdx.y * YSY + (threadIdx.x / YSX);
@@ -1256,231 +1244,64 @@ __global__ __launch_bounds__(256) void k_yee_bhalf(Yee2Args a) {
 }
 
 template <typename real>
-__global__ __launch_bounds__(256) void k_yee_eb(Yee2Args a) {
+__global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
     const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
     const int x = blockIdx.x * YSX + (threadIdx.x & (YSX - 1));
     const int y = blockIdx.y * YSY + (threadIdx.x / YSX);
     if (x >= nx || y >= ny) return;
     const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
-    const real dt = (real)a.dt, hdt = (real)(0.5 * a.dt);
+    const real dt = (real)a.dt;
     const real *Ex = (const real *)a.E[0], *Ey = (const real *)a.E[1], *Ez = (const real *)a.E[2];
     const real *Jx = (const real *)a.J[0], *Jy = (const real *)a.J[1], *Jz = (const real *)a.J[2];
     const real *Hx = (const real *)a.B[0], *Hy = (const real *)a.B[1], *Hz = (const real *)a.B[2];
     const size_t sxy = (size_t)nx * ny;
-    const int xp = x + 1 == nx ? 0 : x + 1, yp = y + 1 == ny ? 0 : y + 1;
     const int xm = x == 0 ? nx - 1 : x - 1, ym = y == 0 ? ny - 1 : y - 1;
-    // columns: P, +x, +y, -x, -y, +x-y, -x+y
-    const size_t c0 = (size_t)x + (size_t)nx * y, cxp = (size_t)xp + (size_t)nx * y,
-                 cyp = (size_t)x + (size_t)nx * yp, cxm = (size_t)xm + (size_t)nx * y,
-                 cym = (size_t)x + (size_t)nx * ym, cxpym = (size_t)xp + (size_t)nx * ym,
-                 cxmyp = (size_t)xm + (size_t)nx * yp;
-    // carried from plane k-1: Bh_x, Bh_y at P-z, +x-z (x only), +y-z (y only)
+    const size_t c0 = (size_t)x + (size_t)nx * y, cxm = (size_t)xm + (size_t)nx * y, cym = (size_t)x + (size_t)nx * ym;
     const size_t gm = sxy * (z0 == 0 ? nz - 1 : z0 - 1);
     real hx_m = Hx[c0 + gm], hy_m = Hy[c0 + gm];
-    real hx_xm = Hx[cxp + gm];   // Bh_x(P+x-z)
-    real hy_ym = Hy[cyp + gm];   // Bh_y(P+y-z)
-    // E^{n+1}_x, E^{n+1}_y at P of the first plane (later carried as the +z values)
-    real hx0, hy0, hz0;
-    real e1x, e1y;
-    {
-        const size_t gk = sxy * z0;
-        hx0 = Hx[c0 + gk];
-        hy0 = Hy[c0 + gk];
-        hz0 = Hz[c0 + gk];
-        const real hzym = Hz[cym + gk], hzxm = Hz[cxm + gk];
-        e1x = Ex[c0 + gk] + dt * (((hz0 - hzym) - (hy0 - hy_m)) - Jx[c0 + gk]);
-        e1y = Ey[c0 + gk] + dt * (((hx0 - hx_m) - (hz0 - hzxm)) - Jy[c0 + gk]);
-    }
     for (int k = z0; k < z1; ++k) {
-        const size_t gk = sxy * k, gn = sxy * (k + 1 == nz ? 0 : k + 1);
-        // Bh on plane k at the columns the curls need
-        const real hyxm = Hy[cxm + gk], hxym = Hx[cym + gk];
-        const real hxx = Hx[cxp + gk], hyx = Hy[cxp + gk], hzx = Hz[cxp + gk];
-        const real hxy = Hx[cyp + gk], hyy = Hy[cyp + gk], hzy = Hz[cyp + gk];
-        const real hxxym = Hx[cxpym + gk], hyxmyp = Hy[cxmyp + gk];
-        // E^{n+1} on plane k: z at P, +x, +y; y at +x; x at +y
-        const real e1z = Ez[c0 + gk] + dt * (((hy0 - hyxm) - (hx0 - hxym)) - Jz[c0 + gk]);
-        const real e1zx = Ez[cxp + gk] + dt * (((hyx - hy0) - (hxx - hxxym)) - Jz[cxp + gk]);
-        const real e1zy = Ez[cyp + gk] + dt * (((hyy - hyxmyp) - (hxy - hx0)) - Jz[cyp + gk]);
-        const real e1yx = Ey[cxp + gk] + dt * (((hxx - hx_xm) - (hzx - hz0)) - Jy[cxp + gk]);
-        const real e1xy = Ex[cyp + gk] + dt * (((hzy - hz0) - (hyy - hy_ym)) - Jx[cyp + gk]);
-        // plane k+1: Bh there and E^{n+1}_x, E^{n+1}_y at P+z
-        const real hxn = Hx[c0 + gn], hyn = Hy[c0 + gn], hzn = Hz[c0 + gn];
-        const real hznym = Hz[cym + gn], hznxm = Hz[cxm + gn];
-        const real e1xn = Ex[c0 + gn] + dt * (((hzn - hznym) - (hyn - hy0)) - Jx[c0 + gn]);
-        const real e1yn = Ey[c0 + gn] + dt * (((hxn - hx0) - (hzn - hznxm)) - Jy[c0 + gn]);
-        // outputs at P
-        const size_t g = c0 + gk;
-        ((real *)a.Eo[0])[g] = e1x;
-        ((real *)a.Eo[1])[g] = e1y;
-        ((real *)a.Eo[2])[g] = e1z;
-        ((real *)a.Bo[0])[g] = hx0 - hdt * ((e1zy - e1z) - (e1yn - e1y));
-        ((real *)a.Bo[1])[g] = hy0 - hdt * ((e1xn - e1x) - (e1zx - e1z));
-        ((real *)a.Bo[2])[g] = hz0 - hdt * ((e1yx - e1y) - (e1xy - e1x));
+        const size_t gk = sxy * k, g = c0 + gk;
+        const real hx = Hx[g], hy = Hy[g], hz = Hz[g];
+        const real hzym = Hz[cym + gk], hzxm = Hz[cxm + gk], hyxm = Hy[cxm + gk], hxym = Hx[cym + gk];
+        ((real *)a.Eo[0])[g] = Ex[g] + dt * (((hz - hzym) - (hy - hy_m)) - Jx[g]);
+        ((real *)a.Eo[1])[g] = Ey[g] + dt * (((hx - hx_m) - (hz - hzxm)) - Jy[g]);
+        ((real *)a.Eo[2])[g] = Ez[g] + dt * (((hy - hyxm) - (hx - hxym)) - Jz[g]);
         ((real *)a.Z[0])[g] = (real)0;
         ((real *)a.Z[1])[g] = (real)0;
         ((real *)a.Z[2])[g] = (real)0;
-        // carry to plane k+1
-        hx_m = hx0;
-        hy_m = hy0;
-        hx_xm = hxx;
-        hy_ym = hyy;
-        hx0 = hxn;
-        hy0 = hyn;
-        hz0 = hzn;
-        e1x = e1xn;
-        e1y = e1yn;
+        hx_m = hx;
+        hy_m = hy;
     }
 }
 
-constexpr int YTX = 32, YTY = 8, YPX = YTX + 3, YPY = YTY + 3, YPN = YPX * YPY;
-
-struct YeeArgs {
-    const void *E[3], *B[3], *J[3];
-    void *Eo[3], *Bo[3], *Z[3];
-    int n[3];
-    int zc;       // planes per block
-    double dt;
-};
-
 template <typename real>
-__global__ __launch_bounds__(256) void k_yee_fused(YeeArgs a) {
-    extern __shared__ __align__(16) unsigned char ysm[];
-    real *base = reinterpret_cast<real *>(ysm);
-    // plane buffers, 3 components each
-    real *En[2], *Bh[2], *Ep[2], *Bn, *Jn;
-    En[0] = base;
-    En[1] = En[0] + 3 * YPN;
-    Bh[0] = En[1] + 3 * YPN;
-    Bh[1] = Bh[0] + 3 * YPN;
-    Ep[0] = Bh[1] + 3 * YPN;
-    Ep[1] = Ep[0] + 3 * YPN;
-    Bn = Ep[1] + 3 * YPN;
-    Jn = Bn + 3 * YPN;
-    const real *E0 = (const real *)a.E[0], *E1 = (const real *)a.E[1], *E2 = (const real *)a.E[2];
-    const real *B0 = (const real *)a.B[0], *B1 = (const real *)a.B[1], *B2 = (const real *)a.B[2];
+__global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
     const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-    const int x0 = blockIdx.x * YTX, y0 = blockIdx.y * YTY;
-    const int z0 = blockIdx.z * a.zc, z1 = min(nz, z0 + a.zc);
-    const real dt = (real)a.dt, hdt = (real)(0.5 * a.dt);
-    const int tid = threadIdx.x;
+    const int x = blockIdx.x * YSX + (threadIdx.x & (YSX - 1));
+    const int y = blockIdx.y * YSY + (threadIdx.x / YSX);
+    if (x >= nx || y >= ny) return;
+    const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
+    const real hdt = (real)(0.5 * a.dt);
+    const real *Ex = (const real *)a.Eo[0], *Ey = (const real *)a.Eo[1], *Ez = (const real *)a.Eo[2];
+    const real *Hx = (const real *)a.B[0], *Hy = (const real *)a.B[1], *Hz = (const real *)a.B[2];
     const size_t sxy = (size_t)nx * ny;
-    auto gidx = [&](int li, int lj, int z) -> size_t {
-        int gx = wrap_any(x0 + li, nx), gy = wrap_any(y0 + lj, ny);
-        return (size_t)gx + (size_t)nx * gy + sxy * (size_t)z;
-    };
-    auto at = [](int li, int lj) { return (li + 1) + YPX * (lj + 1); };
-    // load E^n of plane z over offsets [-1, T+1]
-    auto loadE = [&](real *dst, int z) {
-        for (int q = tid; q < YPN; q += 256) {
-            int li = q % YPX - 1, lj = q / YPX - 1;
-            size_t g = gidx(li, lj, z);
-            dst[q] = E0[g];
-            dst[YPN + q] = E1[g];
-            dst[2 * YPN + q] = E2[g];
-        }
-    };
-    // B^{n+1/2} of plane z over [-1, T] from B^n (Bn) and E^n planes z, z+1
-    auto halfB = [&](real *dst, const real *e, const real *ez) {
-        for (int q = tid; q < YPN; q += 256) {
-            int li = q % YPX - 1, lj = q / YPX - 1;
-            if (li > YTX || lj > YTY) continue;
-            int c = at(li, lj), cx = at(li + 1, lj), cy = at(li, lj + 1);
-            real cxv = (e[2 * YPN + cy] - e[2 * YPN + c]) - (ez[YPN + c] - e[YPN + c]);
-            real cyv = (ez[c] - e[c]) - (e[2 * YPN + cx] - e[2 * YPN + c]);
-            real czv = (e[YPN + cx] - e[YPN + c]) - (e[cy] - e[c]);
-            dst[c] = Bn[c] - hdt * cxv;
-            dst[YPN + c] = Bn[YPN + c] - hdt * cyv;
-            dst[2 * YPN + c] = Bn[2 * YPN + c] - hdt * czv;
-        }
-    };
-    int cur = 0;
-    // prologue: E^n(z0-1), E^n(z0), B^n(z0-1) -> B^{n+1/2}(z0-1)
-    const int zm = wrap_any(z0 - 1, nz);
-    loadE(En[cur], zm);
-    loadE(En[1 - cur], z0);
-    for (int q = tid; q < YPN; q += 256) {
-        int li = q % YPX - 1, lj = q / YPX - 1;
-        if (li > YTX || lj > YTY) continue;
-        size_t g = gidx(li, lj, zm);
-        Bn[q] = B0[g];
-        Bn[YPN + q] = B1[g];
-        Bn[2 * YPN + q] = B2[g];
-    }
-    __syncthreads();
-    int hb = 0;  // Bh[hb] holds plane k-1
-    halfB(Bh[hb], En[cur], En[1 - cur]);
-    cur = 1 - cur;  // En[cur] = E^n(z0)
-    int ep = 0;     // Ep[ep] holds E^{n+1}(k-1)
-    __syncthreads();
-    for (int k = z0; k <= z1; ++k) {
-        const int kz = wrap_any(k, nz), kn = wrap_any(k + 1, nz);
-        // E^n(k+1) into the free E plane; B^n(k) and J(k)
-        loadE(En[1 - cur], kn);
-        for (int q = tid; q < YPN; q += 256) {
-            int li = q % YPX - 1, lj = q / YPX - 1;
-            if (li > YTX || lj > YTY) continue;
-            size_t g = gidx(li, lj, kz);
-            Bn[q] = B0[g];
-            Bn[YPN + q] = B1[g];
-            Bn[2 * YPN + q] = B2[g];
-            if (li >= 0 && lj >= 0) {
-                Jn[q] = ((const real *)a.J[0])[g];
-                Jn[YPN + q] = ((const real *)a.J[1])[g];
-                Jn[2 * YPN + q] = ((const real *)a.J[2])[g];
-            }
-        }
-        __syncthreads();
-        halfB(Bh[1 - hb], En[cur], En[1 - cur]);   // B^{n+1/2}(k)
-        __syncthreads();
-        // E^{n+1}(k) over [0, T]
-        {
-            const real *b = Bh[1 - hb], *bz = Bh[hb], *e = En[cur];
-            real *o = Ep[1 - ep];
-            for (int q = tid; q < YPN; q += 256) {
-                int li = q % YPX - 1, lj = q / YPX - 1;
-                if (li < 0 || lj < 0 || li > YTX || lj > YTY) continue;
-                int c = at(li, lj), cx = at(li - 1, lj), cy = at(li, lj - 1);
-                real cxv = (b[2 * YPN + c] - b[2 * YPN + cy]) - (b[YPN + c] - bz[YPN + c]);
-                real cyv = (b[c] - bz[c]) - (b[2 * YPN + c] - b[2 * YPN + cx]);
-                real czv = (b[YPN + c] - b[YPN + cx]) - (b[c] - b[cy]);
-                o[c] = e[c] + dt * (cxv - Jn[c]);
-                o[YPN + c] = e[YPN + c] + dt * (cyv - Jn[YPN + c]);
-                o[2 * YPN + c] = e[2 * YPN + c] + dt * (czv - Jn[2 * YPN + c]);
-            }
-        }
-        __syncthreads();
-        // write E^{n+1}(k); B^{n+1}(k-1) from B^{n+1/2}(k-1) and E^{n+1}(k-1), E^{n+1}(k)
-        for (int q = tid; q < YTX * YTY; q += 256) {
-            int li = q % YTX, lj = q / YTX;
-            if (x0 + li >= nx || y0 + lj >= ny) continue;
-            int c = at(li, lj);
-            if (k < z1) {
-                size_t g = (size_t)(x0 + li) + (size_t)nx * (y0 + lj) + sxy * (size_t)kz;
-                const real *o = Ep[1 - ep];
-                ((real *)a.Eo[0])[g] = o[c];
-                ((real *)a.Eo[1])[g] = o[YPN + c];
-                ((real *)a.Eo[2])[g] = o[2 * YPN + c];
-                ((real *)a.Z[0])[g] = (real)0;
-                ((real *)a.Z[1])[g] = (real)0;
-                ((real *)a.Z[2])[g] = (real)0;
-            }
-            if (k > z0) {
-                const real *e = Ep[ep], *ez = Ep[1 - ep], *bh = Bh[hb];
-                int cx = at(li + 1, lj), cy = at(li, lj + 1);
-                real cxv = (e[2 * YPN + cy] - e[2 * YPN + c]) - (ez[YPN + c] - e[YPN + c]);
-                real cyv = (ez[c] - e[c]) - (e[2 * YPN + cx] - e[2 * YPN + c]);
-                real czv = (e[YPN + cx] - e[YPN + c]) - (e[cy] - e[c]);
-                size_t g = (size_t)(x0 + li) + (size_t)nx * (y0 + lj) + sxy * (size_t)wrap_any(k - 1, nz);
-                ((real *)a.Bo[0])[g] = bh[c] - hdt * cxv;
-                ((real *)a.Bo[1])[g] = bh[YPN + c] - hdt * cyv;
-                ((real *)a.Bo[2])[g] = bh[2 * YPN + c] - hdt * czv;
-            }
-        }
-        __syncthreads();
-        cur = 1 - cur;
-        hb = 1 - hb;
-        ep = 1 - ep;
+    const int xp = x + 1 == nx ? 0 : x + 1, yp = y + 1 == ny ? 0 : y + 1;
+    const size_t col = (size_t)x + (size_t)nx * y, colx = (size_t)xp + (size_t)nx * y,
+                 coly = (size_t)x + (size_t)nx * yp;
+    size_t g = col + sxy * z0;
+    real ex = Ex[g], ey = Ey[g];
+    for (int k = z0; k < z1; ++k) {
+        const size_t gk = sxy * k, gn = sxy * (k + 1 == nz ? 0 : k + 1);
+        const real exn = Ex[col + gn], eyn = Ey[col + gn];
+        const real ez = Ez[col + gk];
+        const real eyx = Ey[colx + gk], ezx = Ez[colx + gk];
+        const real exy = Ex[coly + gk], ezy = Ez[coly + gk];
+        g = col + gk;
+        ((real *)a.Bo[0])[g] = Hx[g] - hdt * ((ezy - ez) - (eyn - ey));
+        ((real *)a.Bo[1])[g] = Hy[g] - hdt * ((exn - ex) - (ezx - ez));
+        ((real *)a.Bo[2])[g] = Hz[g] - hdt * ((eyx - ey) - (exy - ex));
+        ex = exn;
+        ey = eyn;
     }
 }
 
@@ -1488,14 +1309,43 @@ __global__ __launch_bounds__(256) void k_yee_fused(YeeArgs a) {
 // Per-box counts and features
 // ---------------------------------------------------------------------------
 
+// Each wave counts a contiguous run of kBoxRun particles.  The particles are
+// grouped by tile, so a wave's keys rarely change: a wave-uniform running
+// count is kept and flushed with one atomic when the key changes.
+constexpr int kBoxRun = 4096;
+
 template <typename real>
 __global__ void k_box_counts(Particles<real> P, int np, Geom G, unsigned long long *counts) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    int x, y, z;
-    unpack_cell(P.cell[p], x, y, z);
-    int b = box_of_cell(G, x, y, z);
-    wave_count_add(counts, b * G.nsp + P.sp[p]);
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t p0 = w * kBoxRun;
+    if (p0 >= np) return;
+    const int p1 = (int)min((int64_t)np, p0 + kBoxRun);
+    int run_key = -1;
+    unsigned long long run = 0;
+    for (int base = (int)p0; base < p1; base += 64) {
+        const int p = base + lane;
+        int key = -1;
+        if (p < p1) {
+            int x, y, z;
+            unpack_cell(P.cell[p], x, y, z);
+            key = box_of_cell(G, x, y, z) * G.nsp + P.sp[p];
+        }
+        const unsigned long long act = __ballot(key >= 0);
+        const int k0 = __shfl(key, 0);
+        if (__ballot(key == k0) == act) {
+            // the whole wave shares one key
+            if (k0 != run_key) {
+                if (lane == 0 && run) atomicAdd(&counts[run_key], run);
+                run_key = k0;
+                run = 0;
+            }
+            run += (unsigned long long)__popcll(act);
+        } else if (key >= 0) {
+            wave_count_add(counts, key);
+        }
+    }
+    if (lane == 0 && run) atomicAdd(&counts[run_key], run);
 }
 
 // Per-particle pass of the features: per-cell counts, per-box species counts,
@@ -1740,15 +1590,10 @@ hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st) {
     return order == 2 ? gpd_tile<float, 2>(L, st) : gpd_tile<float, 1>(L, st);
 }
 
-static hipError_t launch_yee_fused(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
-
-// The two-pass update writes B^{n+1/2} over the current B buffer, which the
+// The update writes B^{n+1/2} over the current B buffer, which the
 // step no longer needs once the new fields are in the other buffers.
 hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
-#ifdef PB_YEE_FUSED
-    return launch_yee_fused(prec, Y, n, dt, st);
-#endif
-    Yee2Args a;
+    YeeArgs a;
     for (int c = 0; c < 3; ++c) {
         a.E[c] = Y.E[c];
         a.B[c] = Y.B[c];
@@ -1762,49 +1607,24 @@ hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, 
     dim3 grd((n[0] + YSX - 1) / YSX, (n[1] + YSY - 1) / YSY, (n[2] + YSZ - 1) / YSZ);
     if (prec == 8) {
         k_yee_bhalf<double><<<grd, 256, 0, st>>>(a);
-        k_yee_eb<double><<<grd, 256, 0, st>>>(a);
+        k_yee_e<double><<<grd, 256, 0, st>>>(a);
+        k_yee_b2<double><<<grd, 256, 0, st>>>(a);
     } else {
         k_yee_bhalf<float><<<grd, 256, 0, st>>>(a);
-        k_yee_eb<float><<<grd, 256, 0, st>>>(a);
+        k_yee_e<float><<<grd, 256, 0, st>>>(a);
+        k_yee_b2<float><<<grd, 256, 0, st>>>(a);
     }
     return hipGetLastError();
 }
 
-static hipError_t launch_yee_fused(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
-    YeeArgs a;
-    for (int c = 0; c < 3; ++c) {
-        a.E[c] = Y.E[c];
-        a.B[c] = Y.B[c];
-        a.J[c] = Y.J[c];
-        a.Eo[c] = Y.Eo[c];
-        a.Bo[c] = Y.Bo[c];
-        a.Z[c] = Y.Z[c];
-        a.n[c] = n[c];
-    }
-    a.dt = dt;
-    a.zc = n[2] >= 256 ? 32 : (n[2] >= 64 ? 16 : 8);
-    dim3 grd((n[0] + YTX - 1) / YTX, (n[1] + YTY - 1) / YTY, (n[2] + a.zc - 1) / a.zc);
-    size_t lds = (size_t)8 * 3 * YPN * prec;
-    if (prec == 8) {
-        static bool attr = false;
-        if (!attr) {
-            hipError_t e = hipFuncSetAttribute((const void *)k_yee_fused<double>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            attr = true;
-        }
-        k_yee_fused<double><<<grd, 256, lds, st>>>(a);
-    } else {
-        k_yee_fused<float><<<grd, 256, lds, st>>>(a);
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,
                              hipStream_t st) {
     if (np <= 0) return hipSuccess;
-    if (prec == 8) k_box_counts<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(P), np, G, counts);
-    else k_box_counts<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(P), np, G, counts);
+    const int64_t waves = ((int64_t)np + kBoxRun - 1) / kBoxRun;
+    const unsigned grid = (unsigned)((waves + 3) / 4);  // four waves per block
+    if (prec == 8) k_box_counts<double><<<grid, 256, 0, st>>>(cast<double>(P), np, G, counts);
+    else k_box_counts<float><<<grid, 256, 0, st>>>(cast<float>(P), np, G, counts);
     return hipGetLastError();
 }
 
