@@ -29,14 +29,20 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 P = 4  # bytes per float (FP32 workload)
-KERNEL_SRC = os.path.join(ROOT, "paper_2104_11385_amd", "csrc", "pic_kernels.hip")
+# sources that define the gather-push-deposit kernel (its traffic summary is
+# valid only for them)
+KERNEL_SRC = [os.path.join(ROOT, "paper_2104_11385_amd", "csrc", f)
+              for f in ("gpd.hip", "device_util.hpp", "common.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gpd_c2_hbm_traffic.txt")
 
 
 def kernel_source_hash():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():

@@ -17,7 +17,7 @@ INC = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpicbal.so")
 
-HIP_SOURCES = ["pic_kernels.hip", "runtime.hip", "mlp.hip"]
+HIP_SOURCES = ["gpd.hip", "pic_kernels.hip", "runtime.hip", "mlp.hip"]
 HOST_SOURCES = ["lb.cpp"]
 ARCH = os.environ.get("PICBAL_ARCH", "gfx950")
 
