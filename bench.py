@@ -75,6 +75,27 @@ def copy_probe(nbytes=1 << 30, reps=3):
     print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "reps": reps}))
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Achieved HBM bandwidth of a plain device copy (read + write bytes per
+    second, best of reps), the measured ceiling beside the nominal 8 TB/s."""
+    import torch
+    src = torch.ones(nbytes // 4, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
 def workload():
     import picsynth
     return picsynth.config("c2")
@@ -163,6 +184,19 @@ def run_gpu(args):
     timer_stats = {"empty_boxes_zero": bool((costs[~loaded] == 0).all()),
                    "loaded_boxes": int(loaded.sum()),
                    "cv_loaded": float(costs[loaded].std() / costs[loaded].mean()) if loaded.any() else None}
+    # overhead of the device-timer counters: gather-push-deposit kernel time
+    # with the counters on and off, alternated three times
+    on_ms, off_ms = [], []
+    nsteps = max(10, args.steps // 4)
+    for _ in range(3):
+        for flag, acc in ((True, on_ms), (False, off_ms)):
+            ctx.set_cost_timer(flag)
+            _, k, kn_ = timed(mode, False, nsteps, 2, True)
+            acc.append(k[0] / max(1, kn_[0]))
+    ctx.set_cost_timer(True)
+    timer_stats["gpd_ms_timer_on"] = float(np.median(on_ms))
+    timer_stats["gpd_ms_timer_off"] = float(np.median(off_ms))
+    timer_stats["overhead"] = float(np.median(on_ms) / np.median(off_ms) - 1.0)
     ctx.finalize()
     return {
         "n_p": n_p, "ms_per_step": best_ms, "ms_eager_events": ms_step, "ms_graph": ms_graph,
@@ -246,6 +280,14 @@ def uneven_boxes(steps=5, warmup=2):
         ms = (time.perf_counter() - t1) * 1e3 / steps
         res[name] = {"ms_per_step": ms, "particle_steps_per_s": n_p / (ms * 1e-3)}
     res["persistent_over_per_box"] = res["per_box"]["ms_per_step"] / res["persistent"]["ms_per_step"]
+    # algorithmic bytes per step: particles 13P, all cells 15P, cells of
+    # loaded boxes 9P
+    b = wl.boxes.astype(np.int64)
+    bc = (b[:, 3] - b[:, 0]) * (b[:, 4] - b[:, 1]) * (b[:, 5] - b[:, 2])
+    occ = int(bc[wl.species[0].box_ppc > 0].sum())
+    step_bytes = n_p * 13 * P + int(np.prod(wl.n)) * 15 * P + occ * 9 * P
+    res["algorithmic_bytes_per_step"] = step_bytes
+    res["step_hbm_frac"] = step_bytes / (res["persistent"]["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     ctx.finalize()
     return res
 
@@ -290,7 +332,26 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     # decided) and their cost-weighted error on the interval that follows
     model = np.stack([np.maximum(np.expm1(ctx.mlp_predict(f).astype(np.float64)), 0.0) for f in rec["feat"]])
     pred_err = [float(np.abs(model[i] - t).sum() / max(t.sum(), 1e-300)) for i, t in enumerate(rec["timer"])]
+    # cost of one balancing step against the interval it serves: reading the
+    # timer costs, and computing a mapping with each policy
+    ctx.sync()
+    t0 = time.perf_counter()
+    ctx.step(interval)
+    ctx.sync()
+    interval_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    c_now, _ = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
+    read_s = time.perf_counter() - t0
+    lb_s = {}
+    for pname, pol in S.POLICIES.items():
+        t0 = time.perf_counter()
+        pb.lb_distribute(c_now, wl.boxes, ranks, pol)
+        lb_s[pname] = time.perf_counter() - t0
     ctx.finalize()
+    lb_cost = {"interval_ms": interval_s * 1e3, "timer_readback_ms": read_s * 1e3,
+               "readback_frac": read_s / interval_s,
+               "distribute_ms": {k: v * 1e3 for k, v in lb_s.items()},
+               "distribute_frac": {k: v / interval_s for k, v in lb_s.items()}}
     extra["learned_model"] = model
     E = S.evaluate(rec, wl.boxes, ranks, extra=extra)
     summ = S.summary(E)
@@ -317,7 +378,8 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     t0 = time.perf_counter()
     sweep = S.sweep(rec["timer_step"], wl.boxes, ranks)
     sweep_s = time.perf_counter() - t0
-    out = {"E_mean": summ, "loop_replay": loop, "halo_bytes_per_rebalance_mapping": comm,
+    out = {"E_mean": summ, "c_max_over_c_avg": {st: {p: 1.0 / v for p, v in d.items()} for st, d in summ.items()},
+           "balancing_step_cost": lb_cost, "loop_replay": loop, "halo_bytes_per_rebalance_mapping": comm,
            "interval_threshold_sweep": sweep, "sweep_seconds": sweep_s, "rebalances": int(len(rec["timer"]) - 1),
            "learned_over_timer": {p: summ["learned"][p] / summ["timer"][p] for p in summ["timer"]},
            "model_over_timer": {p: summ["learned_model"][p] / summ["timer"][p] for p in summ["timer"]},
@@ -381,6 +443,7 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     r = run_gpu(args)
+    copy_gbs = copy_bandwidth()
     ms = r["ms_per_step"]
     value = r["n_p"] / (ms * 1e-3)
     gpd_gbs = r["gpd_bytes"] / (r["gpd_ms"] * 1e-3) / 1e9
@@ -403,7 +466,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": gpd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gpd_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "gather-push-deposit", "kernel_ms": r["gpd_ms"],
-                     "algorithmic_bytes_per_launch": r["gpd_bytes"]},
+                     "algorithmic_bytes_per_launch": r["gpd_bytes"],
+                     "measured_copy_peak": copy_gbs, "frac_of_copy_peak": gpd_gbs / copy_gbs},
         "step_hbm_frac": r["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "modes_ms_per_step": r["modes_ms"],
         "ms_graph": r["ms_graph"], "ms_eager": r["ms_eager_events"],

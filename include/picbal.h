@@ -289,6 +289,13 @@ PIC_API int pic_mlp_get_weights(pic_ctx *ctx, float *w, int64_t n);
 
 /* ---- measurement ------------------------------------------------------- */
 
+/* Device-timer cost counters on (enable != 0, the default) or off.  Off, the
+ * gather-push-deposit kernel reads no clock and updates no per-box counter,
+ * so DEVICE_TIMER and DEVICE_RTC costs stop accumulating; this measures the
+ * counters' own overhead (the paper calls the GPU-clock strategy's cost
+ * negligible, Sec. 5).  Synchronises the stream when the setting changes. */
+PIC_API int pic_set_cost_timer(pic_ctx *ctx, int32_t enable);
+
 /* With enable != 0 the library brackets each launch of the gather-push-
  * deposit kernel and of the field update with HIP events on its stream. */
 PIC_API int pic_kernel_timing(pic_ctx *ctx, int32_t enable);

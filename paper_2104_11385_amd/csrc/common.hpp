@@ -77,6 +77,7 @@ struct GpdArgs {
     unsigned long long *rtc;       // [nb]
     unsigned int *slow;            // particles that took the global path
     int mode;
+    int timer;                 // nonzero: per-box clock counters are updated
     int tile_base;             // PER_BOX: first tile of the box
     int species_only;          // PER_BOX: species of this launch
     const int4 *queue;         // PERSISTENT: (tile, begin, end, -)

@@ -687,7 +687,12 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
         }
         __syncthreads();
 
-        unsigned long long c0 = clock64(), r0 = wall_clock64();
+        const bool timed = A.timer != 0;
+        unsigned long long c0 = 0, r0 = 0;
+        if (timed) {
+            c0 = clock64();
+            r0 = wall_clock64();
+        }
         unsigned nslow = 0;
         const int lane = tid & 63, qslot0 = tid & ~63;
         int qn = 0;  // entries in this wave's queue (wave-uniform)
@@ -739,10 +744,12 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             while (w < nw && e >= sQn[w]) e -= sQn[w++];
             if (w < nw) deposit_queued<real, M, TX, TY, TZ, H>(qr, qi, nthr, w * 64 + e, sJ);
         }
-        unsigned long long c1 = clock64(), r1 = wall_clock64();
-        if ((tid & 63) == 0) {
-            atomicAdd(&sCyc, c1 - c0);
-            atomicAdd(&sRtc, r1 - r0);
+        if (timed) {
+            unsigned long long c1 = clock64(), r1 = wall_clock64();
+            if ((tid & 63) == 0) {
+                atomicAdd(&sCyc, c1 - c0);
+                atomicAdd(&sRtc, r1 - r0);
+            }
         }
         if (nslow) atomicAdd(&sSlow, nslow);
         __syncthreads();
@@ -781,8 +788,10 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             }
         }
         if (tid == 0) {
-            atomicAdd(&A.cycles[td.box], sCyc);
-            atomicAdd(&A.rtc[td.box], sRtc);
+            if (timed) {
+                atomicAdd(&A.cycles[td.box], sCyc);
+                atomicAdd(&A.rtc[td.box], sRtc);
+            }
             if (sSlow) atomicAdd(A.slow, sSlow);
         }
         __syncthreads();
@@ -838,6 +847,7 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
     A.rtc = L.rtc;
     A.slow = L.slow;
     A.mode = L.mode;
+    A.timer = L.timer;
     A.tile_base = L.tile_base;
     A.species_only = L.species_only;
     A.queue = L.queue;

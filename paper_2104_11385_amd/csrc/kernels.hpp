@@ -77,6 +77,7 @@ struct GpdLaunch {
     unsigned long long *cycles, *rtc;
     unsigned int *slow;
     int mode;
+    int timer;
     int tile_base;
     int species_only;
     const int4 *queue;

@@ -211,6 +211,7 @@ GpdLaunch pic_ctx::gpd_args() const {
     L.rtc = d_rtc;
     L.slow = d_slow;
     L.mode = mode;
+    L.timer = cost_timer ? 1 : 0;
     L.tile_base = 0;
     L.species_only = -1;
     L.queue = Q.queue;
@@ -1096,6 +1097,18 @@ PIC_API int pic_set_field(pic_ctx *ctx, int32_t comp, const double *in) {
         e = hipMemcpy(dst, t.data(), 4 * N, hipMemcpyHostToDevice);
     }
     return e == hipSuccess ? PIC_OK : ctx->hip_fail(e, "copy field");
+}
+
+PIC_API int pic_set_cost_timer(pic_ctx *ctx, int32_t enable) {
+    CHECK_CTX(ctx);
+    bool on = enable != 0;
+    if (on != ctx->cost_timer) {
+        hipError_t e = hipStreamSynchronize(ctx->st);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamSynchronize");
+        ctx->cost_timer = on;
+        ctx->drop_graphs();
+    }
+    return PIC_OK;
 }
 
 PIC_API int pic_kernel_timing(pic_ctx *ctx, int32_t enable) {

@@ -79,6 +79,7 @@ struct pic_ctx {
 
     // timing
     bool timing = false;
+    bool cost_timer = true;  // per-box clock counters in the gather-push-deposit kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events[4];
     std::pair<hipEvent_t, hipEvent_t> ev_pending{};
     int ev_kind = 0;

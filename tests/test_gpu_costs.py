@@ -122,3 +122,23 @@ def test_heuristic_weight_calibration_small():
     r = calibrate.run(n=(64, 64, 64), box_edge=32, ppc=27, order=2, steps=10, warmup=3)
     assert 0.0 < r["w_particle"] < 1.0 and abs(r["w_particle"] + r["w_cell"] - 1.0) < 1e-12
     assert r["ms_step_full"] > r["ms_step_empty"]
+
+
+def test_cost_timer_switch():
+    from paper_2104_11385_amd import picbal as pb
+    wl = uneven_workload()
+    ctx = make_ctx(wl, load=True)
+    try:
+        ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, True)
+        ctx.set_cost_timer(False)
+        ctx.reset_costs()
+        ctx.step(3)
+        off, _ = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
+        assert (off == 0).all()
+        ctx.set_cost_timer(True)
+        ctx.step(3)
+        on, _ = ctx.box_costs(pb.PIC_COST_DEVICE_TIMER)
+        counts = ctx.box_counts()[:, 0]
+        assert (on[counts > 0] > 0).all() and (on[counts == 0] == 0).all()
+    finally:
+        ctx.finalize()
