@@ -115,7 +115,7 @@ typedef struct {
 typedef struct {
     int32_t tile[3];
     int32_t halo;          /* 1 */
-    int32_t block;         /* threads per block: 256 or 512                    */
+    int32_t block;         /* threads per block: 256, 384 or 512               */
     int32_t chunk;         /* max particles per work item (PERSISTENT mode)    */
     int32_t sort_interval; /* steps between particle sorts (>= 1)              */
     int32_t blocks_per_cu; /* resident blocks per CU for PERSISTENT mode      */

@@ -414,6 +414,26 @@ struct PState {
         }
         w = P.w[p];
     }
+    // Makes the registers count as used here, so the compiler waits for the
+    // loads at this point.  Used on the first particle before the loop
+    // (otherwise that path's pending loads merge into the loop's and every
+    // iteration stalls on the next particle's first load) and on the next
+    // particle before the current one's stores.
+    // Writes the moved particle (cell, offsets, momentum) back to slot p.
+    __device__ __forceinline__ void store(const Particles<real> &P, int p) const {
+        P.cell[p] = cell;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            P.f[d][p] = f[d];
+            P.u[d][p] = u[d];
+        }
+    }
+    __device__ __forceinline__ void settle() const {
+        asm volatile("" : : "v"(cell));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) asm volatile("" : : "v"(f[d]), "v"(u[d]));
+        asm volatile("" : : "v"(w));
+    }
 };
 
 // A particle that changed its reference node inside the staged window: its
@@ -429,7 +449,7 @@ struct Deferred {
 template <typename real, int M, int TX, int TY, int TZ, int H>
 __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, const PState<real> &ps,
                                               const TileDesc &td, real hq, real cq, const real *sEB, double *sJ,
-                                              unsigned &nslow, Deferred<real> &df) {
+                                              unsigned &nslow, Deferred<real> &df, PState<real> &out) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
     int c[3];
     unpack_cell(ps.cell, c[0], c[1], c[2]);
@@ -556,11 +576,11 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
         c[d] = cc;
         f[d] = x;
     }
-    A.P.cell[p] = pack_cell(c[0], c[1], c[2]);
+    out.cell = pack_cell(c[0], c[1], c[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        A.P.f[d][p] = f[d];
-        A.P.u[d][p] = u[d];
+        out.f[d] = f[d];
+        out.u[d] = u[d];
     }
 }
 
@@ -705,13 +725,15 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             // the trip count is the same for every lane of the block
             PState<real> cur;
             if (sb + tid < se) cur.load(A.P, sb + tid);
+            cur.settle();
             for (int base = sb; base < se; base += nthr) {
                 const int p = base + tid;
                 PState<real> nxt;
                 if (p + nthr < se) nxt.load(A.P, p + nthr);
                 Deferred<real> df;
                 df.want = false;
-                if (p < se) push_particle<real, M, TX, TY, TZ, H>(A, p, cur, td, hq, cq, sEB, sJ, nslow, df);
+                PState<real> moved;
+                if (p < se) push_particle<real, M, TX, TY, TZ, H>(A, p, cur, td, hq, cq, sEB, sJ, nslow, df, moved);
                 const unsigned long long mask = __ballot(df.want);
                 if (mask) {
                     const int cnt = __popcll(mask);
@@ -731,6 +753,10 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                     }
                     qn += cnt;
                 }
+                // the next particle's loads are waited for before this one's
+                // stores are issued, so that the wait never covers the stores
+                nxt.settle();
+                if (p < se) moved.store(A.P, p);
                 cur = nxt;
             }
         }
@@ -828,7 +854,7 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
         if (e != hipSuccess) return e;
         attr = true;
     }
-    if (L.block != 256 && L.block != 512) return hipErrorInvalidValue;
+    if (L.block != 256 && L.block != 384 && L.block != 512) return hipErrorInvalidValue;
     GpdArgs<real> A;
     A.P = cast<real>(L.P);
     A.segstart = L.segstart;

@@ -711,7 +711,8 @@ PIC_API int pic_get_tuning(pic_ctx *ctx, pic_tuning *out) {
 PIC_API int pic_set_tuning(pic_ctx *ctx, const pic_tuning *t) {
     CHECK_CTX(ctx);
     if (!t) return ctx->fail(PIC_EINVAL, "null tuning");
-    if (t->block != 256 && t->block != 512) return ctx->fail(PIC_EINVAL, "block must be 256 or 512");
+    if (t->block != 256 && t->block != 384 && t->block != 512)
+        return ctx->fail(PIC_EINVAL, "block must be 256, 384 or 512");
     if (t->chunk < 64 || t->sort_interval < 1 || t->blocks_per_cu < 1 || t->blocks_per_cu > 16)
         return ctx->fail(PIC_EINVAL, "chunk >= 64, sort_interval >= 1, 1 <= blocks_per_cu <= 16");
     if (!gpd_supported(t->tile, t->halo)) return ctx->fail(PIC_EUNSUPPORTED, "tile shape not compiled");
@@ -821,7 +822,7 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
             for (int d = 0; d < 3; ++d)
                 if ((ctx->boxes[b].hi[d] - ctx->boxes[b].lo[d]) % t[d]) ok = false;
         if (!ok) continue;
-        for (int blk : {256, 512}) {
+        for (int blk : {256, 384, 512}) {
             if (gpd_lds_bytes(ctx->prec, ctx->order, t, 1, blk) > 160 * 1024) continue;
             pic_tuning c = base;
             std::memcpy(c.tile, t, sizeof(int) * 3);

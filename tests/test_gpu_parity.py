@@ -110,10 +110,10 @@ def test_fast_particles_take_global_path(precision, order):
 def test_sort_interval_and_tiles_do_not_change_results():
     wl = quad_workload(8, seed=12)
     res = []
-    for tile, si in (((8, 8, 4), 1), ((4, 4, 4), 3), ((8, 4, 4), 50), ((8, 8, 4), 7)):
-        print(f"[parity] tile={tile} sort_interval={si}", flush=True)
+    for tile, si, blk in (((8, 8, 4), 1, 256), ((4, 4, 4), 3, 384), ((8, 4, 4), 50, 512), ((8, 8, 4), 7, 384)):
+        print(f"[parity] tile={tile} sort_interval={si} block={blk}", flush=True)
         ctx = make_ctx(wl, load=False)
-        ctx.set_tuning(tile=tile, sort_interval=si)
+        ctx.set_tuning(tile=tile, sort_interval=si, block=blk)
         F0 = picsynth.random_fields(wl.n, 6, amp=0.03)
         x, u, w, ids, sp, F = set_state(ctx, wl, F0)
         ctx.step(6)
