@@ -297,7 +297,7 @@ def test_yee_div_b_preserved():
     np.testing.assert_allclose(divB(F), d0, rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("m", [1, 2])
+@pytest.mark.parametrize("m", [1, 2, 3])
 def test_pic_step_gauss_law_preserved(m):
     # Full step: div E - rho stays at its initial value at every node, which
     # needs the deposit to conserve charge AND to sit on E's stagger.
