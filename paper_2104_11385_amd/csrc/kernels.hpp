@@ -103,13 +103,15 @@ bool gpd_supported(const int tile[3], int halo);
 size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo, int block);
 // Field buffers of one Yee update: inputs E, B, J; outputs Eo, Bo; Z is the
 // J buffer cleared for the next deposit.
-// Fields of one Yee update: inputs E, B (overwritten with B^{n+1/2}), J;
-// outputs Eo, Bo; Z is the J buffer cleared for the next deposit.
+// Fields of one Yee update: inputs E, B, J; X holds B^{n+1/2} on entry to
+// launch_yee (launch_yee_half computes it from E and B) and B^{n+3/2} on
+// exit; outputs Eo, Bo; Z is the J buffer cleared for the next deposit.
 struct YeeBuffers {
-    const void *E[3], *J[3];
-    void *B[3];
+    const void *E[3], *B[3], *J[3];
+    void *X[3];
     void *Eo[3], *Bo[3], *Z[3];
 };
+hipError_t launch_yee_half(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
 hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
 hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,
                              hipStream_t st);

@@ -295,21 +295,23 @@ __global__ void k_fill(T *a, T v, size_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Yee update in three streaming passes.  Threads own (x, y) columns and march
+// Yee update in streaming passes.  Threads own (x, y) columns and march
 // along z, carrying the z neighbours in registers; x and y neighbours are
-// read through the caches.
-//   pass 1 (in place): B <- B^{n+1/2} = B^n - dt/2 curl E^n
-//   pass 2: E^{n+1} = E^n + dt (curl B^{n+1/2} - J) into the other E buffer,
-//           and the next step's J buffer cleared
-//   pass 3: B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1} into the other B buffer
+// read through the caches.  X is a half-step B buffer.
+//   half:  X = B^{n+1/2} = B^n - dt/2 curl E^n (only when X is not current)
+//   E:     E^{n+1} = E^n + dt (curl X - J) into the other E buffer, and the
+//          next step's J buffer cleared
+//   B:     B^{n+1} = X - dt/2 curl E^{n+1} into the other B buffer, and
+//          X = B^{n+1} - dt/2 curl E^{n+1} = B^{n+3/2}, the next step's half
+//          step (the same curl, so the next update skips the half pass)
 // Curl of E uses forward differences, curl of B backward ones (Yee cell).
 // ---------------------------------------------------------------------------
 
 constexpr int YSX = 64, YSY = 4, YSZ = 4;
 
 struct YeeArgs {
-    const void *E[3], *J[3];
-    void *B[3];             // B^n in, B^{n+1/2} out (pass 1); B^{n+1/2} in (pass 2)
+    const void *E[3], *B[3], *J[3];
+    void *X[3];             // B^{n+1/2} (written by the half pass, read by E; B^{n+3/2} out)
     void *Eo[3], *Bo[3], *Z[3];
     int n[3];
     double dt;
@@ -324,7 +326,8 @@ __global__ __launch_bounds__(256) void k_yee_bhalf(YeeArgs a) {
     const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
     const real hdt = (real)(0.5 * a.dt);
     const real *Ex = (const real *)a.E[0], *Ey = (const real *)a.E[1], *Ez = (const real *)a.E[2];
-    real *Bx = (real *)a.B[0], *By = (real *)a.B[1], *Bz = (real *)a.B[2];
+    const real *Bx = (const real *)a.B[0], *By = (const real *)a.B[1], *Bz = (const real *)a.B[2];
+    real *Xx = (real *)a.X[0], *Xy = (real *)a.X[1], *Xz = (real *)a.X[2];
     const size_t sxy = (size_t)nx * ny;
     const int xp = x + 1 == nx ? 0 : x + 1, yp = y + 1 == ny ? 0 : y + 1;
     const size_t col = (size_t)x + (size_t)nx * y, colx = (size_t)xp + (size_t)nx * y,
@@ -341,9 +344,9 @@ __global__ __launch_bounds__(256) void k_yee_bhalf(YeeArgs a) {
         const real cy = (exn - ex) - (ezx - ez);
         const real cz = (eyx - ey) - (exy - ex);
         g = col + gk;
-        Bx[g] = Bx[g] - hdt * cx;
-        By[g] = By[g] - hdt * cy;
-        Bz[g] = Bz[g] - hdt * cz;
+        Xx[g] = Bx[g] - hdt * cx;
+        Xy[g] = By[g] - hdt * cy;
+        Xz[g] = Bz[g] - hdt * cz;
         ex = exn;
         ey = eyn;
     }
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
     const real dt = (real)a.dt;
     const real *Ex = (const real *)a.E[0], *Ey = (const real *)a.E[1], *Ez = (const real *)a.E[2];
     const real *Jx = (const real *)a.J[0], *Jy = (const real *)a.J[1], *Jz = (const real *)a.J[2];
-    const real *Hx = (const real *)a.B[0], *Hy = (const real *)a.B[1], *Hz = (const real *)a.B[2];
+    const real *Hx = (const real *)a.X[0], *Hy = (const real *)a.X[1], *Hz = (const real *)a.X[2];
     const size_t sxy = (size_t)nx * ny;
     const int xm = x == 0 ? nx - 1 : x - 1, ym = y == 0 ? ny - 1 : y - 1;
     const size_t c0 = (size_t)x + (size_t)nx * y, cxm = (size_t)xm + (size_t)nx * y, cym = (size_t)x + (size_t)nx * ym;
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
     const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
     const real hdt = (real)(0.5 * a.dt);
     const real *Ex = (const real *)a.Eo[0], *Ey = (const real *)a.Eo[1], *Ez = (const real *)a.Eo[2];
-    const real *Hx = (const real *)a.B[0], *Hy = (const real *)a.B[1], *Hz = (const real *)a.B[2];
+    real *Hx = (real *)a.X[0], *Hy = (real *)a.X[1], *Hz = (real *)a.X[2];
     const size_t sxy = (size_t)nx * ny;
     const int xp = x + 1 == nx ? 0 : x + 1, yp = y + 1 == ny ? 0 : y + 1;
     const size_t col = (size_t)x + (size_t)nx * y, colx = (size_t)xp + (size_t)nx * y,
@@ -403,9 +406,16 @@ __global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
         const real eyx = Ey[colx + gk], ezx = Ez[colx + gk];
         const real exy = Ex[coly + gk], ezy = Ez[coly + gk];
         g = col + gk;
-        ((real *)a.Bo[0])[g] = Hx[g] - hdt * ((ezy - ez) - (eyn - ey));
-        ((real *)a.Bo[1])[g] = Hy[g] - hdt * ((exn - ex) - (ezx - ez));
-        ((real *)a.Bo[2])[g] = Hz[g] - hdt * ((eyx - ey) - (exy - ex));
+        const real cx = (ezy - ez) - (eyn - ey);
+        const real cy = (exn - ex) - (ezx - ez);
+        const real cz = (eyx - ey) - (exy - ex);
+        const real bx = Hx[g] - hdt * cx, by = Hy[g] - hdt * cy, bz = Hz[g] - hdt * cz;
+        ((real *)a.Bo[0])[g] = bx;
+        ((real *)a.Bo[1])[g] = by;
+        ((real *)a.Bo[2])[g] = bz;
+        Hx[g] = bx - hdt * cx;
+        Hy[g] = by - hdt * cy;
+        Hz[g] = bz - hdt * cz;
         ex = exn;
         ey = eyn;
     }
@@ -620,33 +630,44 @@ hipError_t launch_fill_f64(double *a, size_t n, hipStream_t st) {
 }
 
 
-// The update writes B^{n+1/2} over the current B buffer, which the
-// step no longer needs once the new fields are in the other buffers.
-hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
+static YeeArgs yee_args(const YeeBuffers &Y, const int n[3], double dt) {
     YeeArgs a;
     for (int c = 0; c < 3; ++c) {
         a.E[c] = Y.E[c];
         a.B[c] = Y.B[c];
         a.J[c] = Y.J[c];
+        a.X[c] = Y.X[c];
         a.Eo[c] = Y.Eo[c];
         a.Bo[c] = Y.Bo[c];
         a.Z[c] = Y.Z[c];
         a.n[c] = n[c];
     }
     a.dt = dt;
-    dim3 grd((n[0] + YSX - 1) / YSX, (n[1] + YSY - 1) / YSY, (n[2] + YSZ - 1) / YSZ);
-    if (prec == 8) {
-        k_yee_bhalf<double><<<grd, 256, 0, st>>>(a);
-        k_yee_e<double><<<grd, 256, 0, st>>>(a);
-        k_yee_b2<double><<<grd, 256, 0, st>>>(a);
-    } else {
-        k_yee_bhalf<float><<<grd, 256, 0, st>>>(a);
-        k_yee_e<float><<<grd, 256, 0, st>>>(a);
-        k_yee_b2<float><<<grd, 256, 0, st>>>(a);
-    }
+    return a;
+}
+
+static dim3 yee_grid(const int n[3]) {
+    return dim3((n[0] + YSX - 1) / YSX, (n[1] + YSY - 1) / YSY, (n[2] + YSZ - 1) / YSZ);
+}
+
+hipError_t launch_yee_half(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
+    YeeArgs a = yee_args(Y, n, dt);
+    if (prec == 8) k_yee_bhalf<double><<<yee_grid(n), 256, 0, st>>>(a);
+    else k_yee_bhalf<float><<<yee_grid(n), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
+hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
+    YeeArgs a = yee_args(Y, n, dt);
+    if (prec == 8) {
+        k_yee_e<double><<<yee_grid(n), 256, 0, st>>>(a);
+        k_yee_b2<double><<<yee_grid(n), 256, 0, st>>>(a);
+    } else {
+        k_yee_e<float><<<yee_grid(n), 256, 0, st>>>(a);
+        k_yee_b2<float><<<yee_grid(n), 256, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,
                              hipStream_t st) {

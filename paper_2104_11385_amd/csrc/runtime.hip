@@ -264,22 +264,42 @@ int pic_ctx::enqueue_step() {
     }
     if ((rc = time_end())) return rc;
     if ((rc = time_begin(1))) return rc;
-    YeeBuffers Y;
-    for (int c = 0; c < 3; ++c) {
-        Y.E[c] = Eb[jcur][c];
-        Y.B[c] = Bb[jcur][c];
-        Y.J[c] = Jb[jcur][c];
-        Y.Eo[c] = Eb[1 - jcur][c];
-        Y.Bo[c] = Bb[1 - jcur][c];
-        Y.Z[c] = Jb[1 - jcur][c];
-    }
+    YeeBuffers Y = yee_buffers();
     HIPC(launch_yee(prec, Y, n, dt, st));
     if ((rc = time_end())) return rc;
     return PIC_OK;
 }
 
+YeeBuffers pic_ctx::yee_buffers() const {
+    YeeBuffers Y;
+    for (int c = 0; c < 3; ++c) {
+        Y.E[c] = Eb[jcur][c];
+        Y.B[c] = Bb[jcur][c];
+        Y.J[c] = Jb[jcur][c];
+        Y.X[c] = Xb[c];
+        Y.Eo[c] = Eb[1 - jcur][c];
+        Y.Bo[c] = Bb[1 - jcur][c];
+        Y.Z[c] = Jb[1 - jcur][c];
+    }
+    return Y;
+}
+
+// Computes the half-step B from the current fields (eagerly, outside any
+// captured graph) when it is not current.
+int pic_ctx::yee_half() {
+    if (xvalid) return PIC_OK;
+    int rc;
+    if ((rc = time_begin(1))) return rc;
+    YeeBuffers Y = yee_buffers();
+    HIPC(launch_yee_half(prec, Y, n, dt, st));
+    if ((rc = time_end())) return rc;
+    xvalid = true;
+    return PIC_OK;
+}
+
 int pic_ctx::step(int nsteps) {
     for (int i = 0; i < nsteps; ++i) {
+        if (int rc = yee_half()) return rc;
         if (steps_since_sort >= std::max(1, tun.sort_interval)) {
             int rc;
             if ((rc = time_begin(2))) return rc;
@@ -558,7 +578,8 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     for (int k = 0; k < 3; ++k) {
         if ((rc = c->dalloc(&c->Eb[0][k], fb)) || (rc = c->dalloc(&c->Bb[0][k], fb)) ||
             (rc = c->dalloc(&c->Eb[1][k], fb)) || (rc = c->dalloc(&c->Bb[1][k], fb)) ||
-            (rc = c->dalloc(&c->Jb[0][k], fb)) || (rc = c->dalloc(&c->Jb[1][k], fb)))
+            (rc = c->dalloc(&c->Jb[0][k], fb)) || (rc = c->dalloc(&c->Jb[1][k], fb)) ||
+            (rc = c->dalloc(&c->Xb[k], fb)))
             return init_fail(c, rc, "");
     }
     for (int b = 0; b < 2; ++b) {
@@ -775,6 +796,7 @@ static int copy_state(pic_ctx *c, StateBackup &bk, bool save) {
             bk.bufs.push_back(p);
         }
     }
+    if (!save) c->xvalid = false;
     for (size_t i = 0; i < items.size(); ++i) {
         if (!items[i].bytes) continue;
         hipError_t e = save ? hipMemcpyAsync(bk.bufs[i], items[i].dev, items[i].bytes, hipMemcpyDeviceToDevice, c->st)
@@ -1088,6 +1110,7 @@ PIC_API int pic_set_field(pic_ctx *ctx, int32_t comp, const double *in) {
     hipError_t e = hipStreamSynchronize(ctx->st);
     if (e != hipSuccess) return ctx->hip_fail(e, "sync");
     double off = comp >= 3 && comp < 6 ? ctx->bext[comp - 3] : 0.0;
+    if (comp < 6) ctx->xvalid = false;  // the half-step B follows E and B
     if (ctx->prec == 8) {
         std::vector<double> t(in, in + N);
         for (size_t i = 0; i < N; ++i) t[i] -= off;

@@ -64,6 +64,12 @@ struct pic_ctx {
     void *Eb[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     void *Bb[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     void *Jb[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    // B half a step ahead of the current E: valid while no field was set
+    // from outside since the last update
+    void *Xb[3] = {nullptr, nullptr, nullptr};
+    bool xvalid = false;
+    int yee_half();
+    pb::YeeBuffers yee_buffers() const;
     int jcur = 0;
     pb::SortScratch W{};
     pb::QueueScratch Q{};
