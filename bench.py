@@ -292,7 +292,7 @@ def uneven_boxes(steps=5, warmup=2):
     return res
 
 
-def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, name="c4", weights=None):
+def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, name="c4", weights=None, epochs=30):
     """Balancing study on the 384x384x768 / 3456-box drifting-slab workload:
     trains the learned model on two runs (seeds 4 and 6, 207,360 samples),
     then scores heuristic, device-timer and learned costs with SFC and
@@ -313,7 +313,7 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     wl.seed = eval_seed
     ctx = ctx_for(wl)
     t0 = time.perf_counter()
-    loss = ctx.mlp_train(X, y, epochs=30, batch=1024, seed=eval_seed)
+    loss = ctx.mlp_train(X, y, epochs=epochs, batch=1024, seed=eval_seed)
     train_s = time.perf_counter() - t0
     rec = S.collect(ctx, steps, interval, learned=True, per_step=True)
     # inference cost on 4096 boxes of features (the mixed-box layout's count)
