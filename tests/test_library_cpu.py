@@ -48,6 +48,56 @@ def test_init_argument_errors():
     assert e.value.code == pb.PIC_EINVAL
 
 
+def _tile16():
+    return picsynth.uniform_boxes((32, 32, 32), 16)
+
+
+def _sp(**kw):
+    a = dict(charge=-1, mass=1, density=0.07, load_mode=1, ppc=2)
+    a.update(kw)
+    return pb.Species(**a)
+
+
+_BAD_INIT = [
+    # (description, n, boxes, species, expected code, message fragment)
+    ("domain beyond the packed-cell x limit", (4096, 32, 32), [[0, 0, 0, 4096, 32, 32]], [_sp()],
+     "EINVAL", "domain size"),
+    ("domain beyond the packed-cell z limit", (32, 32, 2048), [[0, 0, 0, 32, 32, 2048]], [_sp()],
+     "EINVAL", "domain size"),
+    ("box past the domain", (32, 32, 32), [[0, 0, 0, 32, 32, 33]], [_sp()], "EINVAL", "outside"),
+    ("empty box", (32, 32, 32), [[0, 0, 0, 32, 32, 32], [4, 4, 4, 4, 8, 8]], [_sp()], "EINVAL", "empty"),
+    ("overlapping boxes", (32, 32, 32), [[0, 0, 0, 32, 32, 32], [0, 0, 0, 16, 16, 16]], [_sp()],
+     "EINVAL", "overlap"),
+    ("boxes with a gap", (32, 32, 32), None, [_sp()], "EINVAL", "gap"),
+    ("five species", (32, 32, 32), "tile", [_sp()] * 5, "EINVAL", "species"),
+    ("massless species", (32, 32, 32), "tile", [_sp(mass=0.0)], "EINVAL", "mass"),
+    ("zero particles per cell", (32, 32, 32), "tile", [_sp(ppc=0)], "EINVAL", "ppc"),
+    ("loading region past the domain", (32, 32, 32), "tile", [_sp(region_hi=(32, 32, 40))],
+     "EINVAL", "loading region"),
+    ("per-box counts missing", (32, 32, 32), "tile", [_sp(load_mode=2)], "EINVAL", "box_ppc"),
+    ("negative per-box count", (32, 32, 32), "tile", [_sp(load_mode=2, box_ppc=[1, 1, -1, 1, 1, 1, 1, 1])],
+     "EINVAL", "negative"),
+    ("unknown load mode", (32, 32, 32), "tile", [_sp(load_mode=3)], "EINVAL", "load_mode"),
+    ("more than 2^31-1 particles", (1024, 1024, 1024), [[0, 0, 0, 1024, 1024, 1024]], [_sp(ppc=3)],
+     "EUNSUPPORTED", "2^31"),
+]
+
+
+@pytest.mark.parametrize("case", _BAD_INIT, ids=[c[0] for c in _BAD_INIT])
+def test_init_rejects_bad_layouts_before_touching_a_device(case):
+    # every one of these is refused on the host, so the status is the same
+    # with or without a GPU
+    _, n, boxes, species, code, frag = case
+    if boxes == "tile":
+        boxes = _tile16()
+    elif boxes is None:
+        boxes = _tile16()[1:]
+    with pytest.raises(pb.PicError) as e:
+        pb.pic_init(n, boxes, species, 0.5, 2, pb.PIC_FP32, 1)
+    assert e.value.code == getattr(pb, "PIC_" + code), str(e.value)
+    assert frag in str(e.value), str(e.value)
+
+
 def test_lb_argument_errors():
     b = picsynth.uniform_boxes((32, 32, 32), 16)
     with pytest.raises(pb.PicError):
