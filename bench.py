@@ -32,7 +32,7 @@ P = 4  # bytes per float (FP32 workload)
 # sources that define the gather-push-deposit kernel (its traffic summary is
 # valid only for them)
 KERNEL_SRC = [os.path.join(ROOT, "paper_2104_11385_amd", "csrc", f)
-              for f in ("gpd.hip", "device_util.hpp", "common.hpp")]
+              for f in ("gpd_kernel.hpp", "gpd_inst.hip", "device_util.hpp", "common.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gpd_c2_hbm_traffic.txt")
 
 

@@ -119,6 +119,13 @@ typedef struct {
     int32_t chunk;         /* max particles per work item (PERSISTENT mode)    */
     int32_t sort_interval; /* steps between particle sorts (>= 1)              */
     int32_t blocks_per_cu; /* resident blocks per CU for PERSISTENT mode      */
+    int32_t run_sum;       /* 1: particles of a tile are sorted node by node
+                              and the currents of neighbouring particles that
+                              keep a common reference node are summed across
+                              lanes before one LDS add per run; 0: particles
+                              are interleaved over nodes (one particle per
+                              node and rank) and each adds its own current.
+                              Results agree to rounding either way.          */
 } pic_tuning;
 
 /* ---- lifecycle -------------------------------------------------------- */

@@ -18,6 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpicbal.so")
 
 HIP_SOURCES = ["gpd.hip", "pic_kernels.hip", "runtime.hip", "mlp.hip"]
+# gpd_inst.hip is compiled once per (precision, shape order) kernel group
+GPD_GROUPS = [(real, order) for real in ("float", "double") for order in (1, 2, 3)]
 HOST_SOURCES = ["lb.cpp"]
 ARCH = os.environ.get("PICBAL_ARCH", "gfx950")
 
@@ -37,6 +39,11 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
         jobs.append(["hipcc", *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+    for real, order in GPD_GROUPS:
+        obj = os.path.join(BUILD, f"gpd_{real}_{order}.o")
+        objs.append(obj)
+        jobs.append(["hipcc", *HIPCC_FLAGS, f"-DPB_GPD_REAL={real}", f"-DPB_GPD_ORDER={order}", "-c",
+                     os.path.join(CSRC, "gpd_inst.hip"), "-o", obj])
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)

@@ -104,6 +104,101 @@ __device__ inline void wave_sum_add(double *arr, int key, double v) {
     }
 }
 
+// Lane moves inside 16-lane rows through DPP (every lane of the wave must be
+// active): row_shr<S> gives lane i the value of lane i - S, row_shl<S> that
+// of lane i + S; lanes whose source lies outside their row receive 0.
+template <int S>
+__device__ __forceinline__ int row_shr(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x110 + S, 0xF, 0xF, true);
+}
+template <int S>
+__device__ __forceinline__ int row_shl(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x100 + S, 0xF, 0xF, true);
+}
+template <int S>
+__device__ __forceinline__ float row_shr(float v) {
+    return __int_as_float(row_shr<S>(__float_as_int(v)));
+}
+template <int S>
+__device__ __forceinline__ double row_shr(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = row_shr<S>((int)b), hi = row_shr<S>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Segments of equal keys in a 16-lane row (contiguous runs, keys never 0):
+// m[j] = 1 when lanes i - 2^j .. i all hold lane i's key, else 0.
+template <typename real>
+struct RowRuns {
+    real m[4];
+    bool last;  // lane i is the last lane of its run inside its row
+    __device__ __forceinline__ void set(int key) {
+        int f1 = row_shr<1>(key) == key;
+        int f2 = f1 & row_shr<1>(f1);
+        int f4 = f2 & row_shr<2>(f2);
+        int f8 = f4 & row_shr<4>(f4);
+        m[0] = (real)f1;
+        m[1] = (real)f2;
+        m[2] = (real)f4;
+        m[3] = (real)f8;
+        last = row_shl<1>(key) != key;
+    }
+    // Inclusive segmented sum: the last lane of each run receives the run's
+    // sum inside the row (Hillis-Steele steps 1, 2, 4, 8).
+    __device__ __forceinline__ real sum(real v) const {
+        v = fma(row_shr<1>(v), m[0], v);
+        v = fma(row_shr<2>(v), m[1], v);
+        v = fma(row_shr<4>(v), m[2], v);
+        v = fma(row_shr<8>(v), m[3], v);
+        return v;
+    }
+    // The same sum of N single-precision values, one v_fmac_f32 with a DPP
+    // source per value and step (v += m * v[lane - S]; lanes whose source
+    // lies outside the row read 0).  The compiler does not fold its own DPP
+    // moves into fmac, which would take two instructions per step.
+    template <int N>
+    __device__ __forceinline__ void sum_n(float (&v)[N]) const;
+};
+
+// Each statement starts with two wait states: a DPP read of a VGPR written
+// by the instruction just before it needs them.
+#define PB_FMAC_STEP6(SH, v, k, m)                                                         \
+    asm volatile("s_nop 1\n\t"                                                            \
+                 "v_fmac_f32_dpp %0, %0, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+                 "v_fmac_f32_dpp %1, %1, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+                 "v_fmac_f32_dpp %2, %2, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+                 "v_fmac_f32_dpp %3, %3, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+                 "v_fmac_f32_dpp %4, %4, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+                 "v_fmac_f32_dpp %5, %5, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1"     \
+                 : "+v"(v[k]), "+v"(v[k + 1]), "+v"(v[k + 2]), "+v"(v[k + 3]), "+v"(v[k + 4]),   \
+                   "+v"(v[k + 5])                                                           \
+                 : "v"(m))
+#define PB_FMAC_STEP2(SH, v, k, m)                                                         \
+    asm volatile("s_nop 1\n\t"                                                            \
+                 "v_fmac_f32_dpp %0, %0, %2 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+                 "v_fmac_f32_dpp %1, %1, %2 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1"     \
+                 : "+v"(v[k]), "+v"(v[k + 1])                                               \
+                 : "v"(m))
+
+template <>
+template <int N>
+__device__ __forceinline__ void RowRuns<float>::sum_n(float (&v)[N]) const {
+    static_assert(N % 2 == 0, "sum_n takes an even count");
+#define PB_FMAC_ALL(SH, mm)                                                                \
+    {                                                                                      \
+        int k = 0;                                                                         \
+        _Pragma("unroll") for (; k + 6 <= N; k += 6) PB_FMAC_STEP6(SH, v, k, mm);          \
+        _Pragma("unroll") for (; k + 2 <= N; k += 2) PB_FMAC_STEP2(SH, v, k, mm);          \
+    }
+    PB_FMAC_ALL("row_shr:1", m[0]);
+    PB_FMAC_ALL("row_shr:2", m[1]);
+    PB_FMAC_ALL("row_shr:4", m[2]);
+    PB_FMAC_ALL("row_shr:8", m[3]);
+#undef PB_FMAC_ALL
+}
+#undef PB_FMAC_STEP6
+#undef PB_FMAC_STEP2
+
 // Box, tile and cell-in-tile of global cell (x, y, z).
 __device__ __forceinline__ int box_of_cell(const Geom &G, int x, int y, int z) {
     return G.coarse_box[(x / G.g[0]) + G.cg[0] * ((y / G.g[1]) + G.cg[1] * (z / G.g[2]))];

@@ -1,899 +1,15 @@
-// gfx950 gather-push-deposit kernel of the PIC step, with the in-kernel
-// per-box clock costs.
-//
-// Numerical methods (the paper names the PIC scheme only in words, Sec. 2.1):
-//   shapes   centred B-splines of order 1, 2 or 3;
-//   gather   each component interpolated at its own Yee stagger with the same
-//            order-m spline;
-//   push     relativistic Boris rotation (Boris 1970; Birdsall & Langdon);
-//   deposit  Esirkepov (2001) charge-conserving density decomposition.
-// Per-box costs follow Sec. 2.2 and Fig. 2a: a device clock is read around
-// the compute-intensive work, summed on chip, then added once per block to a
-// global per-box counter.
-#include "device_util.hpp"
+// Host side of the gather-push-deposit kernels: the compiled tile shapes,
+// their LDS footprint and the dispatch to the kernel groups (one object per
+// precision and shape order, built from gpd_inst.hip).
 #include "kernels.hpp"
 
 #include <hip/hip_runtime.h>
 
 namespace pb {
 
-// ---------------------------------------------------------------------------
-// Gather - push - deposit
-// ---------------------------------------------------------------------------
-
-// Compile-time tile configuration.  Positions are referred to the particle's
-// cell (order 1) or nearest node (order 2); the staged E/B window reaches
-// RL_EB below and RH_EB above it, the J window RL_J / RH_J, plus the tile
-// halo H on both sides.
-template <typename real, int M, int TX, int TY, int TZ, int H>
-struct Cfg {
-    static constexpr int RL_EB = (M == 1) ? 1 : 2, RH_EB = (M == 3) ? 2 : 1;
-    static constexpr int RL_J = (M == 1) ? 1 : 2, RH_J = (M == 3) ? 3 : 2;
-    static constexpr int EX = TX + 2 * H + RL_EB + RH_EB;
-    static constexpr int EY = TY + 2 * H + RL_EB + RH_EB;
-    static constexpr int EZ = TZ + 2 * H + RL_EB + RH_EB;
-    static constexpr int JX = TX + 2 * H + RL_J + RH_J;
-    static constexpr int JY = TY + 2 * H + RL_J + RH_J;
-    static constexpr int JZ = TZ + 2 * H + RL_J + RH_J;
-    static constexpr int NEB = EX * EY * EZ;
-    static constexpr int NJ = JX * JY * JZ;
-    // J is accumulated in double: gfx950's LDS atomic add is fast for f64
-    // (and integers) but an order of magnitude slower for f32.
-    static constexpr size_t lds = (size_t)(6 * NEB) * sizeof(real) + (size_t)(3 * NJ) * sizeof(double);
-    // per-thread slot of the deferred-deposit queue: d0[3], D[3], coef, rel
-    static constexpr size_t qslot = 7 * sizeof(real) + sizeof(int);
-};
-
-// Shape factors of one dimension.  Inputs: d = offset from the reference
-// (order 1: cell offset f in [0,1); order 2: node offset in [-1/2, 1/2)).
-// Gather weights at integer nodes (wn, first node at offset bn) and at half
-// nodes (wh, first half node at offset bh, dynamic).
+// Defined in gpd_kernel.hpp and instantiated once per (precision, order).
 template <typename real, int M>
-struct GatherW {
-    real wn[M + 1], wh[M + 1];
-    int bh;
-    // cubic B-spline weights of the nodes at -1, 0, 1, 2 from a point at
-    // fraction t in [0, 1) of its cell
-    __device__ __forceinline__ static void cubic(real t, real *w) {
-        const real sixth = (real)(1.0 / 6.0), tt = (real)(2.0 / 3.0);
-        real u = (real)1 - t;
-        w[0] = sixth * u * u * u;
-        w[1] = tt - t * t + (real)0.5 * t * t * t;
-        w[2] = tt - u * u + (real)0.5 * u * u * u;
-        w[3] = sixth * t * t * t;
-    }
-    __device__ __forceinline__ void set(real d) {
-        if (M == 3) {
-            // reference is the cell; d = offset in [0, 1)
-            cubic(d, wn);
-            bool up = d >= (real)0.5;
-            cubic(up ? d - (real)0.5 : d + (real)0.5, wh);
-            bh = up ? -1 : -2;
-        } else if (M == 1) {
-            wn[0] = (real)1 - d;
-            wn[1] = d;
-            bool up = d >= (real)0.5;
-            real t = up ? d - (real)0.5 : d + (real)0.5;
-            bh = up ? 0 : -1;
-            wh[0] = (real)1 - t;
-            wh[1] = t;
-        } else {
-            const real h = (real)0.5;
-            wn[0] = h * (h - d) * (h - d);
-            wn[1] = (real)0.75 - d * d;
-            wn[2] = h * (h + d) * (h + d);
-            bool up = d >= (real)0;
-            real t = up ? d - h : d + h;
-            bh = up ? -1 : -2;
-            wh[0] = h * (h - t) * (h - t);
-            wh[1] = (real)0.75 - t * t;
-            wh[2] = h * (h + t) * (h + t);
-        }
-    }
-};
-
-// Esirkepov window of one dimension: (M+2) nodes starting at offset s from
-// the reference; S0 = old shape, dS = new - old shape.  When the particle
-// keeps its reference node the differences are formed from the
-// displacement itself (no cancellation).
-template <typename real, int M>
-struct DepW {
-    real S0[M + 2], dS[M + 2];
-    int s;
-    bool moved;  // the particle left its reference cell / node this step
-    __device__ __forceinline__ void set(real d0, real D) {
-        real d1 = d0 + D;
-        if (M == 3) {
-            // reference is the cell, d0 in [0, 1); nodes at offsets -1..2
-            int k = (d1 >= (real)1) - (d1 < (real)0);
-            real f1 = d1 - (real)k;
-            bool km = k < 0, kp = k > 0;
-            real o[4], n[4];
-            GatherW<real, 3>::cubic(d0, o);
-            GatherW<real, 3>::cubic(f1, n);
-            // window of 5 nodes from offset s = min(0, k) - 1
-            S0[0] = km ? (real)0 : o[0];
-            S0[1] = km ? o[0] : o[1];
-            S0[2] = km ? o[1] : o[2];
-            S0[3] = km ? o[2] : o[3];
-            S0[4] = km ? o[3] : (real)0;
-            real s1[5];
-            s1[0] = kp ? (real)0 : n[0];
-            s1[1] = kp ? n[0] : n[1];
-            s1[2] = kp ? n[1] : n[2];
-            s1[3] = kp ? n[2] : n[3];
-            s1[4] = kp ? n[3] : (real)0;
-#pragma unroll
-            for (int a = 0; a < 5; ++a) dS[a] = s1[a] - S0[a];
-            if (k == 0) {
-                // differences formed from the displacement D = d1 - d0:
-                // with Q(a, b) = a^2 + ab + b^2 and g = 1 - d,
-                //   node -1: -D Q(g0, g1) / 6        node 2: D Q(d0, d1) / 6
-                //   node  0: -D (d0 + d1) + D Q(d0, d1) / 2
-                //   node  1:  D (g0 + g1) - D Q(g0, g1) / 2
-                const real sixth = (real)(1.0 / 6.0), h = (real)0.5;
-                real g0 = (real)1 - d0, g1 = (real)1 - d1;
-                real qf = d0 * d0 + d0 * d1 + d1 * d1, qg = g0 * g0 + g0 * g1 + g1 * g1;
-                dS[0] = -D * sixth * qg;
-                dS[1] = -D * (d0 + d1) + h * D * qf;
-                dS[2] = D * (g0 + g1) - h * D * qg;
-                dS[3] = D * sixth * qf;
-                dS[4] = (real)0;
-            }
-            s = km ? -2 : -1;
-            moved = k != 0;
-        } else if (M == 1) {
-            int k = (d1 >= (real)1) - (d1 < (real)0);
-            real f1 = d1 - (real)k;
-            bool km = k < 0, kp = k > 0;
-            real a0 = (real)1 - d0, b0 = d0;
-            real a1 = (real)1 - f1, b1 = f1;
-            S0[0] = km ? (real)0 : a0;
-            S0[1] = km ? a0 : b0;
-            S0[2] = km ? b0 : (real)0;
-            real s10 = kp ? (real)0 : a1;
-            real s11 = kp ? a1 : b1;
-            real s12 = kp ? b1 : (real)0;
-            dS[0] = s10 - S0[0];
-            dS[1] = s11 - S0[1];
-            dS[2] = s12 - S0[2];
-            if (k == 0) {
-                dS[0] = -D;
-                dS[1] = D;
-                dS[2] = (real)0;
-            }
-            s = km ? -1 : 0;
-            moved = k != 0;
-        } else {
-            const real h = (real)0.5;
-            int k = (d1 >= h) - (d1 < -h);
-            real e = d1 - (real)k;
-            bool km = k < 0, kp = k > 0;
-            real A0 = h * (h - d0) * (h - d0), B0 = (real)0.75 - d0 * d0, C0 = h * (h + d0) * (h + d0);
-            real A1 = h * (h - e) * (h - e), B1 = (real)0.75 - e * e, C1 = h * (h + e) * (h + e);
-            S0[0] = km ? (real)0 : A0;
-            S0[1] = km ? A0 : B0;
-            S0[2] = km ? B0 : C0;
-            S0[3] = km ? C0 : (real)0;
-            real s1[4];
-            s1[0] = kp ? (real)0 : A1;
-            s1[1] = kp ? A1 : B1;
-            s1[2] = kp ? B1 : C1;
-            s1[3] = kp ? C1 : (real)0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) dS[a] = s1[a] - S0[a];
-            if (k == 0) {
-                real sg = d0 + d1;
-                dS[0] = -h * D * ((real)1 - sg);
-                dS[1] = -D * sg;
-                dS[2] = h * D * ((real)1 + sg);
-                dS[3] = (real)0;
-            }
-            s = km ? -2 : -1;
-            moved = k != 0;
-        }
-    }
-    // The particle keeps its reference (cell or node): window of M+1 nodes
-    // from offset s, differences from the displacement (no cancellation).
-    __device__ __forceinline__ void set_kept(real d0, real D) {
-        real d1 = d0 + D;
-        if (M == 3) {
-            const real sixth = (real)(1.0 / 6.0), tt = (real)(2.0 / 3.0), h = (real)0.5;
-            real u = (real)1 - d0;
-            S0[0] = sixth * u * u * u;
-            S0[1] = tt - d0 * d0 + h * d0 * d0 * d0;
-            S0[2] = tt - u * u + h * u * u * u;
-            S0[3] = sixth * d0 * d0 * d0;
-            real g0 = (real)1 - d0, g1 = (real)1 - d1;
-            real qf = d0 * d0 + d0 * d1 + d1 * d1, qg = g0 * g0 + g0 * g1 + g1 * g1;
-            dS[0] = -D * sixth * qg;
-            dS[1] = -D * (d0 + d1) + h * D * qf;
-            dS[2] = D * (g0 + g1) - h * D * qg;
-            dS[3] = D * sixth * qf;
-            s = -1;
-        } else if (M == 1) {
-            S0[0] = (real)1 - d0;
-            S0[1] = d0;
-            dS[0] = -D;
-            dS[1] = D;
-            s = 0;
-        } else {
-            const real h = (real)0.5;
-            S0[0] = h * (h - d0) * (h - d0);
-            S0[1] = (real)0.75 - d0 * d0;
-            S0[2] = h * (h + d0) * (h + d0);
-            real sg = d0 + d1;
-            dS[0] = -h * D * ((real)1 - sg);
-            dS[1] = -D * sg;
-            dS[2] = h * D * ((real)1 + sg);
-            s = -1;
-        }
-        moved = false;
-    }
-};
-
-// Whether a displacement D from reference offset d0 leaves the reference
-// cell (orders 1, 3: d0 in [0, 1)) or node (order 2: d0 in [-1/2, 1/2)).
-template <typename real, int M>
-__device__ __forceinline__ bool leaves_ref(real d0, real D) {
-    real d1 = d0 + D;
-    if (M == 2) return d1 >= (real)0.5 || d1 < (real)-0.5;
-    return d1 >= (real)1 || d1 < (real)0;
-}
-
-// Interpolates the six field components from an accessor F(comp, i, j, k)
-// where (i,j,k) are offsets from the particle's reference.
-template <typename real, int M, typename Acc>
-__device__ __forceinline__ void gather6(const Acc &F, const GatherW<real, M> W[3], real EB[6]) {
-    const int bn = (M == 1) ? 0 : -1;
-    // stagger pattern per component: 1 = half node along that axis
-    const int pat[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const real *wx = pat[c][0] ? W[0].wh : W[0].wn;
-        const real *wy = pat[c][1] ? W[1].wh : W[1].wn;
-        const real *wz = pat[c][2] ? W[2].wh : W[2].wn;
-        int ox = pat[c][0] ? W[0].bh : bn;
-        int oy = pat[c][1] ? W[1].bh : bn;
-        int oz = pat[c][2] ? W[2].bh : bn;
-        real acc = (real)0;
-        F.begin(c, ox, oy, oz);
-#pragma unroll
-        for (int k = 0; k <= M; ++k) {
-            real ay = (real)0;
-#pragma unroll
-            for (int j = 0; j <= M; ++j) {
-                real ax = (real)0;
-#pragma unroll
-                for (int i = 0; i <= M; ++i) ax += wx[i] * F.tap(i, j, k);
-                ay += wy[j] * ax;
-            }
-            acc += wz[k] * ay;
-        }
-        EB[c] = acc;
-    }
-}
-
-// Deposits the Esirkepov current through an accessor J.add(comp, a, b, c, v)
-// with (a,b,c) offsets inside the window.  L = M + 2 is the general window;
-// a particle that keeps its reference node in every dimension has all its
-// weight on the first M + 1 nodes and uses L = M + 1 (the last running sum
-// along each axis is then zero by construction and is not deposited).
-// The transverse factor of the density decomposition,
-//   S0_u S0_v + (dS_u S0_v + S0_u dS_v) / 2 + dS_u dS_v / 3,
-// equals A_u S0_v + B_u dS_v with A = S0 + dS/2 and B = S0/2 + dS/3; the
-// charge factor -q w / dt is folded into A and B.
-template <typename real, int M, int L, typename Acc>
-__device__ __forceinline__ void deposit3(Acc &J, const DepW<real, M> W[3], real coef) {
-    const real h = (real)0.5, third = (real)(1.0 / 3.0);
-    real Ax[L], Bx[L], Ay[L], By[L];
-#pragma unroll
-    for (int a = 0; a < L; ++a) {
-        Ax[a] = coef * (W[0].S0[a] + h * W[0].dS[a]);
-        Bx[a] = coef * (h * W[0].S0[a] + third * W[0].dS[a]);
-        Ay[a] = coef * (W[1].S0[a] + h * W[1].dS[a]);
-        By[a] = coef * (h * W[1].S0[a] + third * W[1].dS[a]);
-    }
-    J.begin(W[0].s, W[1].s, W[2].s);
-    // Jx: running sum along x of dSx * (A_y S0_z + B_y dS_z)
-#pragma unroll
-    for (int c = 0; c < L; ++c)
-#pragma unroll
-        for (int b = 0; b < L; ++b) {
-            real in = Ay[b] * W[2].S0[c] + By[b] * W[2].dS[c];
-            real acc = (real)0;
-#pragma unroll
-            for (int a = 0; a < L - 1; ++a) {
-                acc += W[0].dS[a] * in;
-                J.add(0, a, b, c, acc);
-            }
-        }
-    // Jy: running sum along y of dSy * (A_x S0_z + B_x dS_z)
-#pragma unroll
-    for (int c = 0; c < L; ++c)
-#pragma unroll
-        for (int a = 0; a < L; ++a) {
-            real in = Ax[a] * W[2].S0[c] + Bx[a] * W[2].dS[c];
-            real acc = (real)0;
-#pragma unroll
-            for (int b = 0; b < L - 1; ++b) {
-                acc += W[1].dS[b] * in;
-                J.add(1, a, b, c, acc);
-            }
-        }
-    // Jz: running sum along z of dSz * (A_x S0_y + B_x dS_y)
-#pragma unroll
-    for (int b = 0; b < L; ++b)
-#pragma unroll
-        for (int a = 0; a < L; ++a) {
-            real in = Ax[a] * W[1].S0[b] + Bx[a] * W[1].dS[b];
-            real acc = (real)0;
-#pragma unroll
-            for (int c = 0; c < L - 1; ++c) {
-                acc += W[2].dS[c] * in;
-                J.add(2, a, b, c, acc);
-            }
-        }
-}
-
-// Accessors: staged LDS windows (compile-time strides) ...
-template <typename real, typename C>
-struct LdsEB {
-    const real *s;
-    int ref;  // linear LDS index of the reference node (component 0)
-    mutable int base;
-    __device__ __forceinline__ void begin(int c, int ox, int oy, int oz) const {
-        base = c * C::NEB + ref + ox + C::EX * (oy + C::EY * oz);
-    }
-    __device__ __forceinline__ real tap(int i, int j, int k) const {
-        return s[base + i + C::EX * (j + C::EY * k)];
-    }
-};
-
-template <typename real, typename C>
-struct LdsJ {
-    double *s;
-    int ref;
-    int base;
-    __device__ __forceinline__ void begin(int sx, int sy, int sz) {
-        base = ref + sx + C::JX * (sy + C::JY * sz);
-    }
-    __device__ __forceinline__ void add(int comp, int a, int b, int c, real v) {
-        atomic_add_lds(&s[comp * C::NJ + base + a + C::JX * (b + C::JY * c)], (double)v);
-    }
-};
-
-// ... and global arrays with periodic wrap (particles beyond the halo).
-template <typename real>
-struct GlobEB {
-    const real *const *EB;
-    int n[3], r[3];
-    mutable const real *arr;
-    mutable int ix[4], iy[4], iz[4];
-    __device__ __forceinline__ void begin(int c, int ox, int oy, int oz) const {
-        arr = EB[c];
-        for (int q = 0; q < 4; ++q) {
-            ix[q] = wrap_any(r[0] + ox + q, n[0]);
-            iy[q] = wrap_any(r[1] + oy + q, n[1]);
-            iz[q] = wrap_any(r[2] + oz + q, n[2]);
-        }
-    }
-    __device__ __forceinline__ real tap(int i, int j, int k) const {
-        return arr[ix[i] + (size_t)n[0] * (iy[j] + (size_t)n[1] * iz[k])];
-    }
-};
-
-template <typename real>
-struct GlobJ {
-    real *const *J;
-    int n[3], r[3];
-    int ix[5], iy[5], iz[5];
-    __device__ __forceinline__ void begin(int sx, int sy, int sz) {
-        for (int q = 0; q < 5; ++q) {
-            ix[q] = wrap_any(r[0] + sx + q, n[0]);
-            iy[q] = wrap_any(r[1] + sy + q, n[1]);
-            iz[q] = wrap_any(r[2] + sz + q, n[2]);
-        }
-    }
-    __device__ __forceinline__ void add(int comp, int a, int b, int c, real v) {
-        atomic_add_global(&J[comp][ix[a] + (size_t)n[0] * (iy[b] + (size_t)n[1] * iz[c])], v);
-    }
-};
-
-// One particle's state as loaded from HBM.
-template <typename real>
-struct PState {
-    uint32_t cell;
-    real f[3], u[3], w;
-    __device__ __forceinline__ void load(const Particles<real> &P, int p) {
-        cell = P.cell[p];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            f[d] = P.f[d][p];
-            u[d] = P.u[d][p];
-        }
-        w = P.w[p];
-    }
-    // Makes the registers count as used here, so the compiler waits for the
-    // loads at this point.  Used on the first particle before the loop
-    // (otherwise that path's pending loads merge into the loop's and every
-    // iteration stalls on the next particle's first load) and on the next
-    // particle before the current one's stores.
-    // Writes the moved particle (cell, offsets, momentum) back to slot p.
-    __device__ __forceinline__ void store(const Particles<real> &P, int p) const {
-        P.cell[p] = cell;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            P.f[d][p] = f[d];
-            P.u[d][p] = u[d];
-        }
-    }
-    __device__ __forceinline__ void settle() const {
-        asm volatile("" : : "v"(cell));
-#pragma unroll
-        for (int d = 0; d < 3; ++d) asm volatile("" : : "v"(f[d]), "v"(u[d]));
-        asm volatile("" : : "v"(w));
-    }
-};
-
-// A particle that changed its reference node inside the staged window: its
-// wider deposit waits in the wave's queue so that it runs with the other
-// queued particles on full waves rather than on otherwise idle lanes.
-template <typename real>
-struct Deferred {
-    bool want;
-    int rel;          // packed window-relative reference node, +8 per byte
-    real d0[3], D[3], coef;
-};
-
-template <typename real, int M, int TX, int TY, int TZ, int H>
-__device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, const PState<real> &ps,
-                                              const TileDesc &td, real hq, real cq, const real *sEB, double *sJ,
-                                              unsigned &nslow, Deferred<real> &df, PState<real> &out) {
-    using C = Cfg<real, M, TX, TY, TZ, H>;
-    int c[3];
-    unpack_cell(ps.cell, c[0], c[1], c[2]);
-    real f[3] = {ps.f[0], ps.f[1], ps.f[2]};
-    real u[3] = {ps.u[0], ps.u[1], ps.u[2]};
-    real w = ps.w;
-
-    // reference point: cell (order 1) or nearest node (order 2)
-    int ref[3];
-    real d0[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (M == 2) {
-            bool up = f[d] >= (real)0.5;
-            ref[d] = c[d] + (up ? 1 : 0);
-            d0[d] = up ? f[d] - (real)1 : f[d];
-        } else {
-            ref[d] = c[d];
-            d0[d] = f[d];
-        }
-    }
-    const int T[3] = {TX, TY, TZ};
-    const int org[3] = {td.x0, td.y0, td.z0};
-    int rel[3];
-    bool fast = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        rel[d] = wrap_rel(ref[d] - org[d], H, A.n[d]);
-        fast = fast && rel[d] <= T[d] + H - 1;
-    }
-
-    GatherW<real, M> GW[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) GW[d].set(d0[d]);
-    real EB[6];
-    if (fast) {
-        LdsEB<real, C> acc{sEB, (rel[0] + H + C::RL_EB) + C::EX * ((rel[1] + H + C::RL_EB) + C::EY * (rel[2] + H + C::RL_EB)), 0};
-        gather6<real, M>(acc, GW, EB);
-    } else {
-        GlobEB<real> acc;
-        acc.EB = A.EB;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            acc.n[d] = A.n[d];
-            acc.r[d] = ref[d];
-        }
-        gather6<real, M>(acc, GW, EB);
-        ++nslow;
-    }
-    // the arrays hold B minus its uniform external part (whose curl is zero)
-    EB[3] += A.bext[0];
-    EB[4] += A.bext[1];
-    EB[5] += A.bext[2];
-
-    // relativistic Boris rotation
-    real um[3] = {u[0] + hq * EB[0], u[1] + hq * EB[1], u[2] + hq * EB[2]};
-    real ig = rsqrt_r((real)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-    real t[3] = {hq * EB[3] * ig, hq * EB[4] * ig, hq * EB[5] * ig};
-    real t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-    real sf = (real)2 * rcp_r((real)1 + t2);
-    real s[3] = {sf * t[0], sf * t[1], sf * t[2]};
-    real up[3] = {um[0] + (um[1] * t[2] - um[2] * t[1]), um[1] + (um[2] * t[0] - um[0] * t[2]),
-                  um[2] + (um[0] * t[1] - um[1] * t[0])};
-    u[0] = um[0] + (up[1] * s[2] - up[2] * s[1]) + hq * EB[0];
-    u[1] = um[1] + (up[2] * s[0] - up[0] * s[2]) + hq * EB[1];
-    u[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + hq * EB[2];
-    real gi = rsqrt_r((real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    real D[3] = {A.dt * u[0] * gi, A.dt * u[1] * gi, A.dt * u[2] * gi};
-
-    // Esirkepov deposit
-    real coef = cq * w;
-    bool moved = leaves_ref<real, M>(d0[0], D[0]) || leaves_ref<real, M>(d0[1], D[1]) ||
-                 leaves_ref<real, M>(d0[2], D[2]);
-    if (fast) {
-        if (moved) {
-            df.want = true;
-            df.rel = (rel[0] + 8) | ((rel[1] + 8) << 8) | ((rel[2] + 8) << 16);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                df.d0[d] = d0[d];
-                df.D[d] = D[d];
-            }
-            df.coef = coef;
-        } else {
-            DepW<real, M> DW[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) DW[d].set_kept(d0[d], D[d]);
-            LdsJ<real, C> acc{sJ, (rel[0] + H + C::RL_J) + C::JX * ((rel[1] + H + C::RL_J) + C::JY * (rel[2] + H + C::RL_J)), 0};
-            deposit3<real, M, M + 1>(acc, DW, coef);
-        }
-    } else {
-        DepW<real, M> DW[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) DW[d].set(d0[d], D[d]);
-        GlobJ<real> acc;
-        acc.J = A.J;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            acc.n[d] = A.n[d];
-            acc.r[d] = ref[d];
-        }
-        deposit3<real, M, M + 2>(acc, DW, coef);
-    }
-
-    // new canonical position: cell + offset in [0, 1), periodic wrap
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        real x = f[d] + D[d];
-        int k = 0;
-        if (x < (real)0) {
-            x += (real)1;
-            k = -1;
-            if (x >= (real)1) {
-                x = (real)0;
-                k = 0;
-            }
-        } else if (x >= (real)1) {
-            x -= (real)1;
-            k = 1;
-        }
-        int cc = c[d] + k;
-        if (cc < 0) cc += A.n[d];
-        else if (cc >= A.n[d]) cc -= A.n[d];
-        c[d] = cc;
-        f[d] = x;
-    }
-    out.cell = pack_cell(c[0], c[1], c[2]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        out.f[d] = f[d];
-        out.u[d] = u[d];
-    }
-}
-
-// Deposits queue entry s (word k of slot s lives at q[k * stride + s]).
-template <typename real, int M, int TX, int TY, int TZ, int H>
-__device__ __forceinline__ void deposit_queued(const real *qr, const int *qi, int stride, int s, double *sJ) {
-    using C = Cfg<real, M, TX, TY, TZ, H>;
-    {
-        const int pk = qi[s];
-        const int r0 = (pk & 255) - 8, r1 = ((pk >> 8) & 255) - 8, r2 = ((pk >> 16) & 255) - 8;
-        DepW<real, M> DW[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) DW[d].set(qr[d * stride + s], qr[(3 + d) * stride + s]);
-        const real coef = qr[6 * stride + s];
-        LdsJ<real, C> acc{sJ, (r0 + H + C::RL_J) + C::JX * ((r1 + H + C::RL_J) + C::JY * (r2 + H + C::RL_J)), 0};
-        deposit3<real, M, M + 2>(acc, DW, coef);
-    }
-}
-
-// Deposits the first n entries of a wave's queue, one per lane.
-template <typename real, int M, int TX, int TY, int TZ, int H>
-__device__ __forceinline__ void drain_queue(const real *qr, const int *qi, int stride, int slot0, int n, int lane,
-                                            double *sJ) {
-    if (lane < n) deposit_queued<real, M, TX, TY, TZ, H>(qr, qi, stride, slot0 + lane, sJ);
-}
-
-template <typename real, int M, int TX, int TY, int TZ, int H>
-__global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
-    using C = Cfg<real, M, TX, TY, TZ, H>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    real *sEB = reinterpret_cast<real *>(smem_raw);
-    double *sJ = reinterpret_cast<double *>(smem_raw + (size_t)6 * C::NEB * sizeof(real));
-    real *qr = reinterpret_cast<real *>(smem_raw + C::lds);           // [7][blockDim.x]
-    int *qi = reinterpret_cast<int *>(qr + 7 * blockDim.x);          // [blockDim.x]
-    __shared__ unsigned long long sCyc, sRtc;
-    __shared__ unsigned int sSlow;
-    __shared__ int sItem[3];
-    __shared__ int sQn[8];  // queue lengths of the block's waves at the end of an item
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int nsp = A.nsp;
-    const int home = blockIdx.x % kSubQueues;  // blocks are dealt round-robin over the XCDs
-    // windows reach at most JX cells; one conditional wrap suffices unless the
-    // domain is smaller than a window
-    const bool small = A.n[0] < C::JX || A.n[1] < C::JY || A.n[2] < C::JZ;
-    int sq = 0;                                // sub-queues already found empty (thread 0)
-
-    for (int iter = 0;; ++iter) {
-        int tile, pbeg, pend;
-        if (A.mode == MODE_PERSISTENT) {
-            // own XCD's sub-queue first, then steal from the others
-            if (tid == 0) {
-                sItem[0] = -1;
-                for (; sq < kSubQueues; ++sq) {
-                    int x = (home + sq) % kSubQueues;
-                    int lo = A.queue_bounds[x], hi = A.queue_bounds[x + 1];
-                    if (hi <= lo) continue;
-                    int q = atomicAdd(&A.queue_head[x], 1);
-                    if (lo + q < hi) {
-                        int4 it = A.queue[lo + q];
-                        sItem[0] = it.x;
-                        sItem[1] = it.y;
-                        sItem[2] = it.z;
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            tile = sItem[0];
-            pbeg = sItem[1];
-            pend = sItem[2];
-            if (tile < 0) break;
-        } else {
-            if (iter > 0) break;
-            tile = A.tile_base + blockIdx.x;
-            if (A.species_only >= 0) {
-                pbeg = A.segstart[tile * nsp + A.species_only];
-                pend = A.segstart[tile * nsp + A.species_only + 1];
-            } else {
-                pbeg = A.segstart[tile * nsp];
-                pend = A.segstart[(tile + 1) * nsp];
-            }
-            if (pbeg >= pend) break;
-        }
-        const TileDesc td = A.tiles[tile];
-
-        // stage E and B of the tile window (one index computation serves the
-        // six components; windows inside the domain need no wrap); clear the
-        // J window
-        {
-            const int ox = td.x0 - H - C::RL_EB, oy = td.y0 - H - C::RL_EB, oz = td.z0 - H - C::RL_EB;
-            const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::EX <= A.n[0] && oy + C::EY <= A.n[1] &&
-                                oz + C::EZ <= A.n[2];
-            const size_t sy = (size_t)A.n[0], sz = (size_t)A.n[0] * A.n[1];
-            for (int i = tid; i < C::NEB; i += nthr) {
-                int lx = i % C::EX;
-                int r2 = i / C::EX;
-                int ly = r2 % C::EY;
-                int lz = r2 / C::EY;
-                int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-                if (!inside) {
-                    if (small) {
-                        gx = wrap_any(gx, A.n[0]);
-                        gy = wrap_any(gy, A.n[1]);
-                        gz = wrap_any(gz, A.n[2]);
-                    } else {
-                        gx = wrap_near(gx, A.n[0]);
-                        gy = wrap_near(gy, A.n[1]);
-                        gz = wrap_near(gz, A.n[2]);
-                    }
-                }
-                const size_t g = (size_t)gx + sy * gy + sz * gz;
-                real v[6];
-#pragma unroll
-                for (int comp = 0; comp < 6; ++comp) v[comp] = A.EB[comp][g];
-#pragma unroll
-                for (int comp = 0; comp < 6; ++comp) sEB[comp * C::NEB + i] = v[comp];
-            }
-        }
-        for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = 0.0;
-        if (tid == 0) {
-            sCyc = 0;
-            sRtc = 0;
-            sSlow = 0;
-        }
-        __syncthreads();
-
-        const bool timed = A.timer != 0;
-        unsigned long long c0 = 0, r0 = 0;
-        if (timed) {
-            c0 = clock64();
-            r0 = wall_clock64();
-        }
-        unsigned nslow = 0;
-        const int lane = tid & 63, qslot0 = tid & ~63;
-        int qn = 0;  // entries in this wave's queue (wave-uniform)
-        for (int s = 0; s < nsp; ++s) {
-            if (A.mode == MODE_PER_BOX && s != A.species_only) continue;
-            int sb = max(pbeg, A.segstart[tile * nsp + s]);
-            int se = min(pend, A.segstart[tile * nsp + s + 1]);
-            real hq = A.h[s], cq = A.coefq[s];
-            // the next particle's loads are issued before this one is computed;
-            // the trip count is the same for every lane of the block
-            PState<real> cur;
-            if (sb + tid < se) cur.load(A.P, sb + tid);
-            cur.settle();
-            for (int base = sb; base < se; base += nthr) {
-                const int p = base + tid;
-                PState<real> nxt;
-                if (p + nthr < se) nxt.load(A.P, p + nthr);
-                Deferred<real> df;
-                df.want = false;
-                PState<real> moved;
-                if (p < se) push_particle<real, M, TX, TY, TZ, H>(A, p, cur, td, hq, cq, sEB, sJ, nslow, df, moved);
-                const unsigned long long mask = __ballot(df.want);
-                if (mask) {
-                    const int cnt = __popcll(mask);
-                    if (qn + cnt > 64) {
-                        drain_queue<real, M, TX, TY, TZ, H>(qr, qi, nthr, qslot0, qn, lane, sJ);
-                        qn = 0;
-                    }
-                    if (df.want) {
-                        const int s2 = qslot0 + qn + __popcll(mask & ((1ull << lane) - 1ull));
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            qr[d * nthr + s2] = df.d0[d];
-                            qr[(3 + d) * nthr + s2] = df.D[d];
-                        }
-                        qr[6 * nthr + s2] = df.coef;
-                        qi[s2] = df.rel;
-                    }
-                    qn += cnt;
-                }
-                // the next particle's loads are waited for before this one's
-                // stores are issued, so that the wait never covers the stores
-                nxt.settle();
-                if (p < se) moved.store(A.P, p);
-                cur = nxt;
-            }
-        }
-        // the entries left in the waves' queues are deposited by the block
-        // together, one per thread, instead of by each wave on its own
-        if (lane == 0) sQn[tid >> 6] = qn;
-        __syncthreads();
-        {
-            const int nw = nthr >> 6;
-            int e = tid, w = 0;
-            while (w < nw && e >= sQn[w]) e -= sQn[w++];
-            if (w < nw) deposit_queued<real, M, TX, TY, TZ, H>(qr, qi, nthr, w * 64 + e, sJ);
-        }
-        if (timed) {
-            unsigned long long c1 = clock64(), r1 = wall_clock64();
-            if ((tid & 63) == 0) {
-                atomicAdd(&sCyc, c1 - c0);
-                atomicAdd(&sRtc, r1 - r0);
-            }
-        }
-        if (nslow) atomicAdd(&sSlow, nslow);
-        __syncthreads();
-
-        // flush the J window (nonzero entries only)
-        {
-            const int ox = td.x0 - H - C::RL_J, oy = td.y0 - H - C::RL_J, oz = td.z0 - H - C::RL_J;
-            const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::JX <= A.n[0] && oy + C::JY <= A.n[1] &&
-                                oz + C::JZ <= A.n[2];
-            const size_t sy = (size_t)A.n[0], sz = (size_t)A.n[0] * A.n[1];
-            for (int i = tid; i < C::NJ; i += nthr) {
-                real v[3];
-#pragma unroll
-                for (int comp = 0; comp < 3; ++comp) v[comp] = (real)sJ[comp * C::NJ + i];
-                if (v[0] == (real)0 && v[1] == (real)0 && v[2] == (real)0) continue;
-                int lx = i % C::JX;
-                int r2 = i / C::JX;
-                int ly = r2 % C::JY;
-                int lz = r2 / C::JY;
-                int gx = ox + lx, gy = oy + ly, gz = oz + lz;
-                if (!inside) {
-                    if (small) {
-                        gx = wrap_any(gx, A.n[0]);
-                        gy = wrap_any(gy, A.n[1]);
-                        gz = wrap_any(gz, A.n[2]);
-                    } else {
-                        gx = wrap_near(gx, A.n[0]);
-                        gy = wrap_near(gy, A.n[1]);
-                        gz = wrap_near(gz, A.n[2]);
-                    }
-                }
-                const size_t g = (size_t)gx + sy * gy + sz * gz;
-#pragma unroll
-                for (int comp = 0; comp < 3; ++comp)
-                    if (v[comp] != (real)0) atomic_add_global(&A.J[comp][g], v[comp]);
-            }
-        }
-        if (tid == 0) {
-            if (timed) {
-                atomicAdd(&A.cycles[td.box], sCyc);
-                atomicAdd(&A.rtc[td.box], sRtc);
-            }
-            if (sSlow) atomicAdd(A.slow, sSlow);
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Host launcher
-// ---------------------------------------------------------------------------
-
-template <typename real>
-static Particles<real> cast(const ParticlesRaw &r) {
-    Particles<real> p;
-    p.cell = r.cell;
-    for (int d = 0; d < 3; ++d) {
-        p.f[d] = (real *)r.f[d];
-        p.u[d] = (real *)r.u[d];
-    }
-    p.w = (real *)r.w;
-    p.id = r.id;
-    p.sp = r.sp;
-    return p;
-}
-
-// Table of compiled gather-push-deposit variants.
-template <typename real, int M, int TX, int TY, int TZ, int H>
-static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
-    using C = Cfg<real, M, TX, TY, TZ, H>;
-    auto kern = k_gpd<real, M, TX, TY, TZ, H>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(C::lds + 512 * C::qslot));
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    if (L.block != 256 && L.block != 384 && L.block != 512) return hipErrorInvalidValue;
-    GpdArgs<real> A;
-    A.P = cast<real>(L.P);
-    A.segstart = L.segstart;
-    A.tiles = L.tiles;
-    for (int c = 0; c < 6; ++c) A.EB[c] = (const real *)L.EB[c];
-    for (int c = 0; c < 3; ++c) A.J[c] = (real *)L.J[c];
-    for (int d = 0; d < 3; ++d) A.n[d] = L.n[d];
-    A.nsp = L.nsp;
-    A.dt = (real)L.dt;
-    for (int d = 0; d < 3; ++d) A.bext[d] = (real)L.bext[d];
-    for (int s = 0; s < kMaxSpecies; ++s) {
-        A.h[s] = (real)L.h[s];
-        A.coefq[s] = (real)L.coefq[s];
-    }
-    A.cycles = L.cycles;
-    A.rtc = L.rtc;
-    A.slow = L.slow;
-    A.mode = L.mode;
-    A.timer = L.timer;
-    A.tile_base = L.tile_base;
-    A.species_only = L.species_only;
-    A.queue = L.queue;
-    A.queue_bounds = L.queue_bounds;
-    A.queue_head = L.queue_head;
-    if (L.grid == 0) return hipSuccess;
-    kern<<<L.grid, L.block, C::lds + (size_t)L.block * C::qslot, st>>>(A);
-    return hipGetLastError();
-}
-
-template <typename real, int M>
-static hipError_t gpd_tile(const GpdLaunch &L, hipStream_t st) {
-    const int *T = L.tile;
-    if (L.halo != 1) return hipErrorInvalidValue;
-    if (T[0] == 8 && T[1] == 8 && T[2] == 8) return gpd_one<real, M, 8, 8, 8, 1>(L, st);
-    if (T[0] == 8 && T[1] == 8 && T[2] == 4) return gpd_one<real, M, 8, 8, 4, 1>(L, st);
-    if (T[0] == 8 && T[1] == 4 && T[2] == 4) return gpd_one<real, M, 8, 4, 4, 1>(L, st);
-    if (T[0] == 4 && T[1] == 4 && T[2] == 4) return gpd_one<real, M, 4, 4, 4, 1>(L, st);
-    return hipErrorInvalidValue;
-}
+hipError_t gpd_tile(const GpdLaunch &L, hipStream_t st);
 
 bool gpd_supported(const int tile[3], int halo) {
     if (halo != 1) return false;

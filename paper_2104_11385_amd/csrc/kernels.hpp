@@ -85,12 +85,13 @@ struct GpdLaunch {
     int *queue_head;
     int tile[3];
     int halo;
+    int run_sum;               // kept-node currents summed over lane runs
     unsigned grid, block;
 };
 
 hipError_t launch_load(int prec, const ParticlesRaw &P, const LoadArgs &a, hipStream_t st);
 hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, int np, const Geom &G,
-                       const SortScratch &W, hipStream_t st);
+                       const SortScratch &W, bool node_major, hipStream_t st);
 hipError_t launch_queue(const int *segstart, int ntiles, int nsp, int chunk, const QueueScratch &Q, hipStream_t st);
 hipError_t launch_set_int(int *p, int v, hipStream_t st);
 hipError_t launch_reset_heads(int *heads, hipStream_t st);

@@ -88,9 +88,11 @@ __global__ void k_load(Particles<real> P, LoadArgs a) {
 
 // ---------------------------------------------------------------------------
 // Tile sort.  Output order: by (tile, species), and inside a (tile, species)
-// segment by (rank of the particle within its cell, cell).  Consecutive
-// particles then sit in distinct cells, so the lanes of a wave deposit into
-// distinct LDS addresses.  A particle belongs to the box of its cell (that
+// segment either by cell (node_major: the particles of a cell are adjacent,
+// so lanes of a wave that share a cell can sum their currents across lanes)
+// or by (rank of the particle within its cell, cell) (consecutive particles
+// then sit in distinct cells, so the lanes of a wave deposit into distinct
+// LDS addresses without summing).  A particle belongs to the box of its cell (that
 // box's timer pays for it, as the box counts say); inside the box, quadratic
 // shapes use the nearest node as the "cell", which fixes the start of the
 // deposit window and centres the tile's halo margin.  A node on the box's
@@ -120,7 +122,21 @@ __global__ void k_sort_key(Particles<real> P, int np, Geom G, uint32_t *cellcnt,
     locate_in_box(G, b, x, y, z, t, l);
     uint32_t k = (uint32_t)((t * G.nsp + P.sp[p]) * G.Tvol + l);
     key[p] = k;
-    rank[p] = atomicAdd(&cellcnt[k], 1u);
+    // Lanes that hold a run of equal keys (a node-major input keeps a
+    // node's particles together) take one atomic per run: the run's first
+    // lane reserves the run's length and the others count on from it.
+    const int lane = (int)__lane_id();
+    const unsigned long long active = __ballot(1);  // the inactive lanes are the wave's last
+    const uint32_t kprev = (uint32_t)__shfl_up((int)k, 1);
+    const unsigned long long starts = __ballot(lane == 0 || kprev != k) | ~active;
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int first = 63 - __clzll(starts & upto);
+    const unsigned long long after = starts & ~upto;
+    const int end = after ? __ffsll((long long)after) - 1 : 64;
+    uint32_t base = 0;
+    if (lane == first) base = atomicAdd(&cellcnt[k], (uint32_t)(end - first));
+    base = (uint32_t)__shfl((int)base, first);
+    rank[p] = base + (uint32_t)(lane - first);
 }
 
 __global__ void k_sort_seg(const uint32_t *cellcnt, uint32_t *cellstart, int *segtot, int Tvol) {
@@ -204,7 +220,7 @@ __global__ void k_sort_scatter(Particles<real> S, Particles<real> D, int np, con
     uint32_t k = key[p];
     int ts = (int)(k / (uint32_t)Tvol);
     int idx = segstart[ts] + (int)cellstart[k] + (int)rank[p];
-    int d = (int)table[idx];
+    int d = table ? (int)table[idx] : idx;
     D.cell[d] = S.cell[p];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -246,19 +262,19 @@ __global__ void k_queue_count(const int *segstart, int ntiles, int nsp, int chun
     if (rem) atomicAdd(&cls_cnt[x * ncls + size_class(rem, chunk, ncls)], 1);
 }
 
-// Bucket offsets: sub-queue major, size class (largest first) minor.
+// Bucket offsets: sub-queue major, size class (largest first) minor.  One
+// block with a thread per bucket (kSubQueues * ncls, a multiple of 64 and at
+// most 1024); the counts are cleared for the next build.
 __global__ void k_queue_scan(int *cls_cnt, int *cursor, int ncls, int *qbounds) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int acc = 0;
-    for (int x = 0; x < kSubQueues; ++x) {
-        qbounds[x] = acc;
-        for (int c = 0; c < ncls; ++c) {
-            cursor[x * ncls + c] = acc;
-            acc += cls_cnt[x * ncls + c];
-            cls_cnt[x * ncls + c] = 0;
-        }
-    }
-    qbounds[kSubQueues] = acc;
+    __shared__ int sh[17];
+    const int i = threadIdx.x;
+    const int v = cls_cnt[i];
+    int tot;
+    const int ex = block_excl_scan(v, sh, tot);
+    cursor[i] = ex;
+    cls_cnt[i] = 0;
+    if (i % ncls == 0) qbounds[i / ncls] = ex;
+    if (i == 0) qbounds[kSubQueues] = tot;
 }
 
 __global__ void k_queue_fill(const int *segstart, int ntiles, int nsp, int chunk, int ncls, int *cursor,
@@ -554,7 +570,7 @@ hipError_t launch_load(int prec, const ParticlesRaw &P, const LoadArgs &a, hipSt
 }
 
 hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, int np, const Geom &G,
-                       const SortScratch &W, hipStream_t st) {
+                       const SortScratch &W, bool node_major, hipStream_t st) {
     int nts = W.nseg;
     size_t ncells = (size_t)nts * G.Tvol;
     k_fill<uint32_t><<<std::min<size_t>(4096, (ncells + 255) / 256), 256, 0, st>>>(W.cellcnt, 0u, ncells);
@@ -571,21 +587,26 @@ hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, i
         k_scan_single<<<1, 1024, 0, st>>>(W.bsum, W.boff, nblk1);
         k_scan_apply<<<nblk1, 1024, 0, st>>>(W.segtot, nts, W.boff, W.segstart);
     }
-    k_sort_levels<<<nts, G.Tvol, 0, st>>>(W.cellcnt, W.cellstart, W.segstart, W.table, G.Tvol);
+    const uint32_t *table = nullptr;
+    if (!node_major) {
+        k_sort_levels<<<nts, G.Tvol, 0, st>>>(W.cellcnt, W.cellstart, W.segstart, W.table, G.Tvol);
+        table = W.table;
+    }
     if (np > 0) {
         if (prec == 8)
             k_sort_scatter<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(S), cast<double>(D), np, W.key, W.rank,
-                                                                   W.cellstart, W.segstart, W.table, G.Tvol);
+                                                                   W.cellstart, W.segstart, table, G.Tvol);
         else
             k_sort_scatter<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(S), cast<float>(D), np, W.key, W.rank,
-                                                                 W.cellstart, W.segstart, W.table, G.Tvol);
+                                                                 W.cellstart, W.segstart, table, G.Tvol);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_queue(const int *segstart, int ntiles, int nsp, int chunk, const QueueScratch &Q, hipStream_t st) {
+    if (Q.ncls < 8 || Q.ncls > 1024 / kSubQueues || (kSubQueues * Q.ncls) % 64) return hipErrorInvalidValue;
     k_queue_count<<<nblk(ntiles, 256), 256, 0, st>>>(segstart, ntiles, nsp, chunk, Q.ncls, Q.cls_cnt);
-    k_queue_scan<<<1, 64, 0, st>>>(Q.cls_cnt, Q.cursor, Q.ncls, Q.queue_bounds);
+    k_queue_scan<<<1, kSubQueues * Q.ncls, 0, st>>>(Q.cls_cnt, Q.cursor, Q.ncls, Q.queue_bounds);
     k_queue_fill<<<nblk(ntiles, 256), 256, 0, st>>>(segstart, ntiles, nsp, chunk, Q.ncls, Q.cursor, Q.queue);
     return hipGetLastError();
 }

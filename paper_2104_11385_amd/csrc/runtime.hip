@@ -25,6 +25,17 @@ thread_local std::string g_init_error;
 // Autotuner results, shared by contexts of the same workload signature.
 std::map<std::string, pic_tuning> g_tune_cache;
 
+// LDS of one gfx950 compute unit.
+constexpr size_t kLdsPerCu = 160 * 1024;
+
+// Blocks of the gather-push-deposit kernel that the LDS of one CU holds at
+// once (1 to 4).
+int resident_blocks(int prec, int order, const int tile[3], int block) {
+    size_t lds = gpd_lds_bytes(prec, order, tile, 1, block);
+    int n = lds ? (int)(kLdsPerCu / lds) : 1;
+    return n < 1 ? 1 : (n > 4 ? 4 : n);
+}
+
 const char *status_text(int code) {
     switch (code) {
     case PIC_OK: return "ok";
@@ -178,7 +189,7 @@ void pic_ctx::free_tile_buffers() {
 
 int pic_ctx::sort_now() {
     int next = 1 - pcur;
-    HIPC(launch_sort(prec, P[pcur], P[next], (int)np, geom(), W, st));
+    HIPC(launch_sort(prec, P[pcur], P[next], (int)np, geom(), W, tun.run_sum != 0, st));
     pcur = next;
     steps_since_sort = 0;
     int chunk = std::max(64, tun.chunk);
@@ -218,6 +229,7 @@ GpdLaunch pic_ctx::gpd_args() const {
     L.queue_bounds = Q.queue_bounds;
     L.queue_head = Q.queue_head;
     L.halo = tun.halo;
+    L.run_sum = tun.run_sum;
     L.block = (unsigned)tun.block;
     L.grid = 0;
     return L;
@@ -548,17 +560,17 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
         c->own_stream = true;
     }
 
-    // default tuning: largest compiled tile that divides every box edge and
-    // leaves room for two resident blocks per CU
+    // default tuning: the largest compiled tile that divides every box edge
+    // and leaves room for three resident 256-thread blocks per CU, else for
+    // two, else for one; as many persistent blocks per CU as the LDS holds
     c->tun.halo = 1;
     c->tun.block = 256;
     c->tun.chunk = 4096;
     c->tun.sort_interval = 20;
-    c->tun.blocks_per_cu = 2;
+    c->tun.run_sum = 1;
     const int cand[4][3] = {{8, 4, 4}, {4, 4, 4}, {8, 8, 4}, {8, 8, 8}};
-    // first choice: two blocks per CU fit the LDS; else any tile that fits
     bool chosen = false;
-    for (size_t limit : {(size_t)80 * 1024, (size_t)160 * 1024}) {
+    for (size_t limit : {(size_t)kLdsPerCu / 3, (size_t)kLdsPerCu / 2, (size_t)kLdsPerCu}) {
         for (auto &t : cand) {
             if (chosen) break;
             bool ok = true;
@@ -571,6 +583,7 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
         }
     }
     if (!chosen) return init_fail(c, PIC_EUNSUPPORTED, "no compiled tile divides every box edge and fits the LDS");
+    c->tun.blocks_per_cu = resident_blocks(c->prec, c->order, c->tun.tile, 256);
 
     int rc;
     size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
@@ -736,8 +749,9 @@ PIC_API int pic_set_tuning(pic_ctx *ctx, const pic_tuning *t) {
         return ctx->fail(PIC_EINVAL, "block must be 256, 384 or 512");
     if (t->chunk < 64 || t->sort_interval < 1 || t->blocks_per_cu < 1 || t->blocks_per_cu > 16)
         return ctx->fail(PIC_EINVAL, "chunk >= 64, sort_interval >= 1, 1 <= blocks_per_cu <= 16");
+    if (t->run_sum != 0 && t->run_sum != 1) return ctx->fail(PIC_EINVAL, "run_sum must be 0 or 1");
     if (!gpd_supported(t->tile, t->halo)) return ctx->fail(PIC_EUNSUPPORTED, "tile shape not compiled");
-    if (gpd_lds_bytes(ctx->prec, ctx->order, t->tile, t->halo, t->block) > 160 * 1024)
+    if (gpd_lds_bytes(ctx->prec, ctx->order, t->tile, t->halo, t->block) > kLdsPerCu)
         return ctx->fail(PIC_EUNSUPPORTED, "tile needs more LDS than a CU has");
     for (int b = 0; b < ctx->nb; ++b)
         for (int d = 0; d < 3; ++d)
@@ -833,8 +847,9 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
         if (ms_per_step) *ms_per_step = -1.0;
         return PIC_OK;
     }
-    // candidates: every compiled tile that fits, two block sizes; then chunk
-    // and residency for the persistent queue around the best of those
+    // candidates: every compiled tile that fits, three block sizes; then the
+    // other particle order, and chunk and residency for the persistent queue,
+    // around the best of those
     std::vector<pic_tuning> cand;
     const int tiles[4][3] = {{8, 4, 4}, {4, 4, 4}, {8, 8, 4}, {8, 8, 8}};
     pic_tuning base = ctx->tun;
@@ -845,10 +860,11 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
                 if ((ctx->boxes[b].hi[d] - ctx->boxes[b].lo[d]) % t[d]) ok = false;
         if (!ok) continue;
         for (int blk : {256, 384, 512}) {
-            if (gpd_lds_bytes(ctx->prec, ctx->order, t, 1, blk) > 160 * 1024) continue;
+            if (gpd_lds_bytes(ctx->prec, ctx->order, t, 1, blk) > kLdsPerCu) continue;
             pic_tuning c = base;
             std::memcpy(c.tile, t, sizeof(int) * 3);
             c.block = blk;
+            c.blocks_per_cu = resident_blocks(ctx->prec, ctx->order, t, blk);
             cand.push_back(c);
         }
     }
@@ -891,9 +907,21 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
             win = t;
         }
     }
+    if (!rc) {
+        pic_tuning t = win;
+        t.run_sum = 1 - win.run_sum;
+        double ms;
+        rc = trial(t, ms);
+        if (!rc && ms < win_ms) {
+            win_ms = ms;
+            win = t;
+        }
+    }
     if (!rc && ctx->mode == PIC_LAUNCH_PERSISTENT) {
-        for (int chunk : {1024, 2048, 8192}) {
-            for (int bpc : {1, 2, 4}) {
+        const int fit = resident_blocks(ctx->prec, ctx->order, win.tile, win.block);
+        for (int chunk : {1024, 2048, 4096, 8192}) {
+            for (int bpc : {fit - 1, fit, fit + 1}) {
+                if (bpc < 1 || (chunk == win.chunk && bpc == win.blocks_per_cu)) continue;
                 pic_tuning t = win;
                 t.chunk = chunk;
                 t.blocks_per_cu = bpc;

@@ -107,13 +107,32 @@ def test_fast_particles_take_global_path(precision, order):
     compare(ctx, wl, x, u, w, sp, ids, F, 10, TOL[precision])
 
 
+@pytest.mark.parametrize("precision", [8, 4])
+@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("run_sum", [0, 1])
+def test_dense_nodes_both_particle_orders(precision, order, run_sum):
+    # 24 particles per cell: a node's particles fill more than one 16-lane
+    # row, so the lane sums of the node-major order span row boundaries; the
+    # interleaved order deposits particle by particle.  Both match the oracle.
+    wl = picsynth.small_workload(n=(16, 8, 16), box=8, order=order, ppc=24, seed=31, species=("electrons",),
+                                 u_th=0.02, precision=precision, region_lo=(0, 0, 4), region_hi=(16, 8, 12))
+    print(f"[parity] dense nodes order={order} precision={precision} run_sum={run_sum}", flush=True)
+    ctx = make_ctx(wl, load=False)
+    ctx.set_tuning(run_sum=run_sum, sort_interval=4)
+    F0 = picsynth.random_fields(wl.n, 13, amp=0.04)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+    ctx.step(10)
+    compare(ctx, wl, x, u, w, sp, ids, F, 10, TOL[precision])
+
+
 def test_sort_interval_and_tiles_do_not_change_results():
     wl = quad_workload(8, seed=12)
     res = []
-    for tile, si, blk in (((8, 8, 4), 1, 256), ((4, 4, 4), 3, 384), ((8, 4, 4), 50, 512), ((8, 8, 4), 7, 384)):
-        print(f"[parity] tile={tile} sort_interval={si} block={blk}", flush=True)
+    for tile, si, blk, rs in (((8, 8, 4), 1, 256, 1), ((4, 4, 4), 3, 384, 0), ((8, 4, 4), 50, 512, 1),
+                              ((8, 8, 4), 7, 384, 0)):
+        print(f"[parity] tile={tile} sort_interval={si} block={blk} run_sum={rs}", flush=True)
         ctx = make_ctx(wl, load=False)
-        ctx.set_tuning(tile=tile, sort_interval=si, block=blk)
+        ctx.set_tuning(tile=tile, sort_interval=si, block=blk, run_sum=rs)
         F0 = picsynth.random_fields(wl.n, 6, amp=0.03)
         x, u, w, ids, sp, F = set_state(ctx, wl, F0)
         ctx.step(6)
