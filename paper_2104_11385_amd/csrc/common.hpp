@@ -76,6 +76,7 @@ struct GpdArgs {
     unsigned long long *cycles;    // [nb]
     unsigned long long *rtc;       // [nb]
     unsigned int *slow;            // particles that took the global path
+    int *jdirty;                   // [n[2]] set to 1 for every z-plane of J written
     int mode;
     int timer;                 // nonzero: per-box clock counters are updated
     int tile_base;             // PER_BOX: first tile of the box

@@ -392,6 +392,7 @@ struct GlobEB {
 template <typename real>
 struct GlobJ {
     real *const *J;
+    int *jdirty;
     int n[3], r[3];
     int ix[5], iy[5], iz[5];
     __device__ __forceinline__ void begin(int sx, int sy, int sz) {
@@ -399,6 +400,7 @@ struct GlobJ {
             ix[q] = wrap_any(r[0] + sx + q, n[0]);
             iy[q] = wrap_any(r[1] + sy + q, n[1]);
             iz[q] = wrap_any(r[2] + sz + q, n[2]);
+            jdirty[iz[q]] = 1;
         }
     }
     __device__ __forceinline__ void add(int comp, int a, int b, int c, real v) {
@@ -555,6 +557,7 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
         for (int d = 0; d < 3; ++d) DW[d].set(d0[d], D[d]);
         GlobJ<real> acc;
         acc.J = A.J;
+        acc.jdirty = A.jdirty;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             acc.n[d] = A.n[d];
@@ -883,6 +886,11 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::JX <= A.n[0] && oy + C::JY <= A.n[1] &&
                                 oz + C::JZ <= A.n[2];
             const size_t sy = (size_t)A.n[0], sz = (size_t)A.n[0] * A.n[1];
+            // the window's z-planes may now hold current
+            if (tid < C::JZ) {
+                const int gz = oz + tid;
+                A.jdirty[small ? wrap_any(gz, A.n[2]) : wrap_near(gz, A.n[2])] = 1;
+            }
             for (int i = tid; i < C::NJ; i += nthr) {
                 real v[3];
 #pragma unroll
@@ -969,6 +977,7 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
     A.cycles = L.cycles;
     A.rtc = L.rtc;
     A.slow = L.slow;
+    A.jdirty = L.jdirty;
     A.mode = L.mode;
     A.timer = L.timer;
     A.tile_base = L.tile_base;

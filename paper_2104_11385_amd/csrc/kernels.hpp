@@ -76,6 +76,7 @@ struct GpdLaunch {
     double coefq[kMaxSpecies];
     unsigned long long *cycles, *rtc;
     unsigned int *slow;
+    int *jdirty;               // [nz] z-planes of J the deposit touched
     int mode;
     int timer;
     int tile_base;
@@ -97,7 +98,7 @@ hipError_t launch_set_int(int *p, int v, hipStream_t st);
 hipError_t launch_reset_heads(int *heads, hipStream_t st);
 hipError_t launch_fill_f(int prec, void *a, double v, size_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *a, size_t n, hipStream_t st);
-hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st, uint32_t v = 0);
 hipError_t launch_fill_f64(double *a, size_t n, hipStream_t st);
 hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st);
 bool gpd_supported(const int tile[3], int halo);
@@ -107,10 +108,14 @@ size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo, int block
 // Fields of one Yee update: inputs E, B, J; X holds B^{n+1/2} on entry to
 // launch_yee (launch_yee_half computes it from E and B) and B^{n+3/2} on
 // exit; outputs Eo, Bo; Z is the J buffer cleared for the next deposit.
+// jdirty / zdirty: per z-plane occupancy flags of J and Z (0: the plane is
+// zero); launch_yee resets zdirty.
 struct YeeBuffers {
     const void *E[3], *B[3], *J[3];
     void *X[3];
     void *Eo[3], *Bo[3], *Z[3];
+    const int *jdirty;
+    int *zdirty;
 };
 hipError_t launch_yee_half(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
 hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);

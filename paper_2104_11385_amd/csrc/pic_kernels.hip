@@ -316,7 +316,8 @@ __global__ void k_fill(T *a, T v, size_t n) {
 // read through the caches.  X is a half-step B buffer.
 //   half:  X = B^{n+1/2} = B^n - dt/2 curl E^n (only when X is not current)
 //   E:     E^{n+1} = E^n + dt (curl X - J) into the other E buffer, and the
-//          next step's J buffer cleared
+//          next step's J buffer cleared; z-planes that the deposit left
+//          untouched (J occupancy flag 0) are neither read nor cleared
 //   B:     B^{n+1} = X - dt/2 curl E^{n+1} into the other B buffer, and
 //          X = B^{n+1} - dt/2 curl E^{n+1} = B^{n+3/2}, the next step's half
 //          step (the same curl, so the next update skips the half pass)
@@ -329,6 +330,8 @@ struct YeeArgs {
     const void *E[3], *B[3], *J[3];
     void *X[3];             // B^{n+1/2} (written by the half pass, read by E; B^{n+3/2} out)
     void *Eo[3], *Bo[3], *Z[3];
+    const int *jdirty;      // [nz] 0: plane of J known to be zero
+    int *zdirty;            // [nz] the same for Z; reset by the B pass once Z is clear
     int n[3];
     double dt;
 };
@@ -386,14 +389,23 @@ __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
     real hx_m = Hx[c0 + gm], hy_m = Hy[c0 + gm];
     for (int k = z0; k < z1; ++k) {
         const size_t gk = sxy * k, g = c0 + gk;
+        const bool jd = a.jdirty[k] != 0, zd = a.zdirty[k] != 0;
         const real hx = Hx[g], hy = Hy[g], hz = Hz[g];
         const real hzym = Hz[cym + gk], hzxm = Hz[cxm + gk], hyxm = Hy[cxm + gk], hxym = Hx[cym + gk];
-        ((real *)a.Eo[0])[g] = Ex[g] + dt * (((hz - hzym) - (hy - hy_m)) - Jx[g]);
-        ((real *)a.Eo[1])[g] = Ey[g] + dt * (((hx - hx_m) - (hz - hzxm)) - Jy[g]);
-        ((real *)a.Eo[2])[g] = Ez[g] + dt * (((hy - hyxm) - (hx - hxym)) - Jz[g]);
-        ((real *)a.Z[0])[g] = (real)0;
-        ((real *)a.Z[1])[g] = (real)0;
-        ((real *)a.Z[2])[g] = (real)0;
+        real jx = (real)0, jy = (real)0, jz = (real)0;
+        if (jd) {
+            jx = Jx[g];
+            jy = Jy[g];
+            jz = Jz[g];
+        }
+        ((real *)a.Eo[0])[g] = Ex[g] + dt * (((hz - hzym) - (hy - hy_m)) - jx);
+        ((real *)a.Eo[1])[g] = Ey[g] + dt * (((hx - hx_m) - (hz - hzxm)) - jy);
+        ((real *)a.Eo[2])[g] = Ez[g] + dt * (((hy - hyxm) - (hx - hxym)) - jz);
+        if (zd) {
+            ((real *)a.Z[0])[g] = (real)0;
+            ((real *)a.Z[1])[g] = (real)0;
+            ((real *)a.Z[2])[g] = (real)0;
+        }
         hx_m = hx;
         hy_m = hy;
     }
@@ -402,10 +414,12 @@ __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
 template <typename real>
 __global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
     const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+    const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
+    // the E pass (earlier on the stream) has cleared Z: its planes are zero
+    if (blockIdx.x == 0 && blockIdx.y == 0 && (int)threadIdx.x < z1 - z0) a.zdirty[z0 + threadIdx.x] = 0;
     const int x = blockIdx.x * YSX + (threadIdx.x & (YSX - 1));
     const int y = blockIdx.y * YSY + (threadIdx.x / YSX);
     if (x >= nx || y >= ny) return;
-    const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
     const real hdt = (real)(0.5 * a.dt);
     const real *Ex = (const real *)a.Eo[0], *Ey = (const real *)a.Eo[1], *Ez = (const real *)a.Eo[2];
     real *Hx = (real *)a.X[0], *Hy = (real *)a.X[1], *Hz = (real *)a.X[2];
@@ -636,10 +650,10 @@ hipError_t launch_fill_u64(unsigned long long *a, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st) {
+hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st, uint32_t v) {
     unsigned g = (unsigned)std::min<size_t>(8192, (n + 255) / 256);
     if (g == 0) return hipSuccess;
-    k_fill<uint32_t><<<g, 256, 0, st>>>(a, 0u, n);
+    k_fill<uint32_t><<<g, 256, 0, st>>>(a, v, n);
     return hipGetLastError();
 }
 
@@ -663,6 +677,8 @@ static YeeArgs yee_args(const YeeBuffers &Y, const int n[3], double dt) {
         a.Z[c] = Y.Z[c];
         a.n[c] = n[c];
     }
+    a.jdirty = Y.jdirty;
+    a.zdirty = Y.zdirty;
     a.dt = dt;
     return a;
 }

@@ -221,6 +221,7 @@ GpdLaunch pic_ctx::gpd_args() const {
     L.cycles = d_cycles;
     L.rtc = d_rtc;
     L.slow = d_slow;
+    L.jdirty = d_jdirty[jcur];
     L.mode = mode;
     L.timer = cost_timer ? 1 : 0;
     L.tile_base = 0;
@@ -282,6 +283,14 @@ int pic_ctx::enqueue_step() {
     return PIC_OK;
 }
 
+// Marks every z-plane of both J buffers as possibly nonzero (after J was
+// written from outside the step).
+int pic_ctx::mark_j_dirty() {
+    for (int b = 0; b < 2; ++b)
+        if (launch_fill_u32((uint32_t *)d_jdirty[b], (size_t)n[2], st, 1u) != hipSuccess) return PIC_EDEVICE;
+    return PIC_OK;
+}
+
 YeeBuffers pic_ctx::yee_buffers() const {
     YeeBuffers Y;
     for (int c = 0; c < 3; ++c) {
@@ -293,6 +302,8 @@ YeeBuffers pic_ctx::yee_buffers() const {
         Y.Bo[c] = Bb[1 - jcur][c];
         Y.Z[c] = Jb[1 - jcur][c];
     }
+    Y.jdirty = d_jdirty[jcur];
+    Y.zdirty = d_jdirty[1 - jcur];
     return Y;
 }
 
@@ -620,6 +631,8 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     if ((rc = c->dalloc((void **)&c->d_cycles, 8 * (size_t)n_boxes)) ||
         (rc = c->dalloc((void **)&c->d_rtc, 8 * (size_t)n_boxes)) ||
         (rc = c->dalloc((void **)&c->d_slow, sizeof(unsigned))) ||
+        (rc = c->dalloc((void **)&c->d_jdirty[0], sizeof(int) * (size_t)c->n[2])) ||
+        (rc = c->dalloc((void **)&c->d_jdirty[1], sizeof(int) * (size_t)c->n[2])) ||
         (rc = c->dalloc((void **)&c->d_counts, 8 * (size_t)n_boxes * n_species)))
         return init_fail(c, rc, "");
     // box geometry
@@ -652,7 +665,7 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
             return init_fail(c, PIC_EDEVICE, "field initialisation failed");
     }
     if (launch_fill_u64(c->d_cycles, n_boxes, c->st) || launch_fill_u64(c->d_rtc, n_boxes, c->st) ||
-        launch_fill_u32((uint32_t *)c->d_slow, 1, c->st) ||
+        launch_fill_u32((uint32_t *)c->d_slow, 1, c->st) || c->mark_j_dirty() ||
         launch_fill_u32((uint32_t *)c->Q.cls_cnt, (size_t)kSubQueues * c->Q.ncls, c->st))
         return init_fail(c, PIC_EDEVICE, "counter initialisation failed");
 
@@ -810,7 +823,10 @@ static int copy_state(pic_ctx *c, StateBackup &bk, bool save) {
             bk.bufs.push_back(p);
         }
     }
-    if (!save) c->xvalid = false;
+    if (!save) {
+        c->xvalid = false;
+        if (c->mark_j_dirty()) return c->fail(PIC_EDEVICE, "J plane flags");
+    }
     for (size_t i = 0; i < items.size(); ++i) {
         if (!items[i].bytes) continue;
         hipError_t e = save ? hipMemcpyAsync(bk.bufs[i], items[i].dev, items[i].bytes, hipMemcpyDeviceToDevice, c->st)
@@ -1139,6 +1155,7 @@ PIC_API int pic_set_field(pic_ctx *ctx, int32_t comp, const double *in) {
     if (e != hipSuccess) return ctx->hip_fail(e, "sync");
     double off = comp >= 3 && comp < 6 ? ctx->bext[comp - 3] : 0.0;
     if (comp < 6) ctx->xvalid = false;  // the half-step B follows E and B
+    else if (ctx->mark_j_dirty()) return ctx->fail(PIC_EDEVICE, "J plane flags");
     if (ctx->prec == 8) {
         std::vector<double> t(in, in + N);
         for (size_t i = 0; i < N; ++i) t[i] -= off;

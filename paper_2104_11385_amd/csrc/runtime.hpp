@@ -70,6 +70,7 @@ struct pic_ctx {
     bool xvalid = false;
     int yee_half();
     pb::YeeBuffers yee_buffers() const;
+    int mark_j_dirty();
     int jcur = 0;
     pb::SortScratch W{};
     pb::QueueScratch Q{};
@@ -79,6 +80,7 @@ struct pic_ctx {
     // costs
     unsigned long long *d_cycles = nullptr, *d_rtc = nullptr, *d_counts = nullptr;
     unsigned *d_slow = nullptr;
+    int *d_jdirty[2] = {nullptr, nullptr};  // per z-plane: J buffer b may be nonzero there
     std::vector<double> last_timer;      // last device-timer costs read
     std::vector<double> last_pred;       // learned prediction made for the current interval
     double mare = -1.0;                  // last mean relative error of the learned costs
