@@ -724,6 +724,8 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     const bool small = A.n[0] < C::JX || A.n[1] < C::JY || A.n[2] < C::JZ;
     int sq = 0;                                // sub-queues already found empty (thread 0)
 
+    // the J window starts clear; each flush clears what it reads
+    for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = 0.0;
     for (int iter = 0;; ++iter) {
         int tile, pbeg, pend;
         if (A.mode == MODE_PERSISTENT) {
@@ -796,7 +798,6 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 for (int comp = 0; comp < 6; ++comp) sEB[comp * C::NEB + i] = v[comp];
             }
         }
-        for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = 0.0;
         if (tid == 0) {
             sCyc = 0;
             sRtc = 0;
@@ -892,10 +893,16 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 A.jdirty[small ? wrap_any(gz, A.n[2]) : wrap_near(gz, A.n[2])] = 1;
             }
             for (int i = tid; i < C::NJ; i += nthr) {
+                double dv[3];
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) dv[comp] = sJ[comp * C::NJ + i];
+                if (dv[0] == 0.0 && dv[1] == 0.0 && dv[2] == 0.0) continue;
                 real v[3];
 #pragma unroll
-                for (int comp = 0; comp < 3; ++comp) v[comp] = (real)sJ[comp * C::NJ + i];
-                if (v[0] == (real)0 && v[1] == (real)0 && v[2] == (real)0) continue;
+                for (int comp = 0; comp < 3; ++comp) {
+                    v[comp] = (real)dv[comp];
+                    sJ[comp * C::NJ + i] = 0.0;
+                }
                 int lx = i % C::JX;
                 int r2 = i / C::JX;
                 int ly = r2 % C::JY;
