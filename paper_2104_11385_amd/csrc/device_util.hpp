@@ -20,12 +20,14 @@ __device__ __forceinline__ int wrap_near(int i, int n) {
     return i >= n ? i - n : i;
 }
 
-// Wraps a tile-relative coordinate r into [-h, n - h).
+// Wraps a tile-relative coordinate r into [-h, n - h).  Only tiles on a
+// periodic face need the wrap, so the test comes first.
 __device__ __forceinline__ int wrap_rel(int r, int h, int n) {
     int t = r + h;
-    if (t < 0) t += n;
-    else if (t >= n) t -= n;
-    if (t < 0 || t >= n) t = wrap_any(t, n);
+    if ((unsigned)t >= (unsigned)n) {
+        t = t < 0 ? t + n : t - n;
+        if ((unsigned)t >= (unsigned)n) t = wrap_any(t, n);
+    }
     return t - h;
 }
 

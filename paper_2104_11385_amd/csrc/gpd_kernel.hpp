@@ -350,6 +350,10 @@ struct LdsEB {
     mutable int base;
     __device__ __forceinline__ void begin(int c, int ox, int oy, int oz) const {
         base = c * C::NEB + ref + ox + C::EX * (oy + C::EY * oz);
+        // opaque to the optimiser: otherwise it rebases the six components'
+        // taps on one register, and the negative offsets that leaves need an
+        // add each (LDS reads take only non-negative immediate offsets)
+        asm("" : "+v"(base));
     }
     __device__ __forceinline__ real tap(int i, int j, int k) const {
         return s[base + i + C::EX * (j + C::EY * k)];
@@ -363,6 +367,7 @@ struct LdsJ {
     int base;
     __device__ __forceinline__ void begin(int sx, int sy, int sz) {
         base = ref + sx + C::JX * (sy + C::JY * sz);
+        asm("" : "+v"(base));  // as in LdsEB::begin
     }
     __device__ __forceinline__ void add(int comp, int a, int b, int c, real v) {
         atomic_add_lds(&s[comp * C::NJ + base + a + C::JX * (b + C::JY * c)], (double)v);
