@@ -292,7 +292,8 @@ def uneven_boxes(steps=5, warmup=2):
     return res
 
 
-def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, name="c4", weights=None, epochs=30):
+def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, name="c4", weights=None, epochs=30,
+             keep=None):
     """Balancing study on the 384x384x768 / 3456-box drifting-slab workload:
     trains the learned model on two runs (seeds 4 and 6, 207,360 samples),
     then scores heuristic, device-timer and learned costs with SFC and
@@ -332,6 +333,8 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     # decided) and their cost-weighted error on the interval that follows
     model = np.stack([np.maximum(np.expm1(ctx.mlp_predict(f).astype(np.float64)), 0.0) for f in rec["feat"]])
     pred_err = [float(np.abs(model[i] - t).sum() / max(t.sum(), 1e-300)) for i, t in enumerate(rec["timer"])]
+    if keep is not None:
+        keep.update({"weights": ctx.mlp_get_weights(), "X": X, "y": y})
     # cost of one balancing step against the interval it serves: reading the
     # timer costs, and computing a mapping with each policy
     ctx.sync()
@@ -390,6 +393,63 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
            "workload": "384x384x768, 3456 boxes of 32^3, e-/p+ slab z in [374,394) at 16 ppc each drifting "
                        "u_z=0.05, quadratic, FP32; train seeds 4,6; evaluate seed 5"}
     return out
+
+
+def mixed_box_generalisation(weights, X4, y4, steps=60, interval=10, ranks=96, epochs=30):
+    """The learned cost on the 4096 mixed boxes (64^3, 32^3, 16^3) of the
+    512^3 workload, whose box sizes and boundary flags the 32^3-box training
+    runs never show.  A held-out run (box ppc table of seed 3, the benchmark
+    one) is scored with (a) the model trained on the balancing study's runs
+    alone and (b) that training set plus the records of a mixed-box run
+    whose box ppc table comes from another seed (19), so that it shares no
+    box loads with the held-out run.  Reports the cost-weighted error of
+    each model's predictions on the intervals they precede and the
+    efficiency of the mappings they give (96 virtual ranks), beside the
+    heuristic and the device timer."""
+    import picsynth
+    from paper_2104_11385_amd import lb_study as S
+    from paper_2104_11385_amd import picbal as pb
+    t_start = time.perf_counter()
+    wl = picsynth.config("c3")
+    wl.species[0].box_ppc = picsynth.lognormal_box_ppc(len(wl.boxes), 19)
+    wl.seed = 11
+    ctx = ctx_for(wl)
+    ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, True)
+    rec_t = S.collect(ctx, steps, interval)
+    ctx.finalize()
+    X3, y3 = S.training_set([rec_t])
+    wl = picsynth.config("c3")
+    wl.seed = 12
+    ctx = ctx_for(wl)
+    ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, True)
+    ctx.mlp_set_weights(weights)
+    rec = S.collect(ctx, steps, interval, learned=True)
+    def predict():
+        return np.stack([np.maximum(np.expm1(ctx.mlp_predict(f).astype(np.float64)), 0.0) for f in rec["feat"]])
+
+    preds = {"learned_c4_only": predict()}
+    # the mixed-box records alone are 24,576 samples against 207,360: also
+    # weighted up by repetition so that they carry as much of the loss
+    rep = max(1, len(y4) // max(1, len(y3)))
+    for name, (Xt, yt) in {"learned_with_mixed": (np.concatenate([X4, X3]), np.concatenate([y4, y3])),
+                           "learned_with_mixed_weighted": (np.concatenate([X4] + [X3] * rep),
+                                                           np.concatenate([y4] + [y3] * rep))}.items():
+        ctx.mlp_train(Xt, yt, epochs=epochs, batch=1024, seed=12)
+        preds[name] = predict()
+    ctx.finalize()
+
+    def err(pred):
+        return [float(np.abs(pred[i] - t).sum() / max(t.sum(), 1e-300)) for i, t in enumerate(rec["timer"])]
+
+    E = S.summary(S.evaluate(rec, wl.boxes, ranks, extra=preds))
+    return {"E_mean": E,
+            "error_per_interval": {k: err(v) for k, v in preds.items()}, "mixed_repetition": rep,
+            "library_fallbacks_c4_model": int(sum(1 for u in rec["learned_used"] if u != pb.PIC_COST_LEARNED)),
+            "train_samples": {"c4": int(len(y4)), "mixed": int(len(y3))},
+            "rebalances": int(len(rec["timer"]) - 1), "steps": steps, "interval": interval, "ranks": ranks,
+            "wall_s": time.perf_counter() - t_start,
+            "workload": "512^3, 4096 mixed boxes, lognormal box ppc (held out: table seed 3, loader seed 12; "
+                        "added training run: table seed 19, loader seed 11), quadratic, FP32"}
 
 
 def box_edge_sweep(edges=(16, 32, 64, 128), steps=300, interval=10, ranks=96, seed=5):
@@ -484,7 +544,10 @@ def main():
         out["heuristic_calibration"] = cal
         weights = (cal["order2"]["w_particle"], cal["order2"]["w_cell"])
     if not args.no_lb:
-        out["lb_study"] = lb_study(steps=args.lb_steps, weights=weights)
+        keep = {}
+        out["lb_study"] = lb_study(steps=args.lb_steps, weights=weights, keep=keep)
+        if not args.no_c3:
+            out["learned_on_mixed_boxes"] = mixed_box_generalisation(keep["weights"], keep["X"], keep["y"])
     if args.lb_edges:
         out["lb_box_edges"] = box_edge_sweep(steps=args.lb_steps)
     if not args.no_cpu:
