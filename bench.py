@@ -28,6 +28,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# fp32 vector peak of the 256 CUs at 2.4 GHz: 4 SIMDs x 16 lanes x FMA (2 flops)
+# per CU and clock without packed-FP32 instructions (which this build does not
+# use), and with them
+FP32_VECTOR_PEAK_TFS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_PACKED_PEAK_TFS = 2 * FP32_VECTOR_PEAK_TFS
+# Arithmetic of one particle-step of a particle that keeps its reference node,
+# by shape order (counted for quadratic shapes from the kernel's formulas, an
+# FMA counting 2 and the shape factors shared between gather and deposit):
+# gather 444 (weights 51, six staggered components 390, external B 3),
+# Boris rotation 66, move 12, Esirkepov deposit 229.
+FLOPS_PER_PARTICLE_STEP = {2: 751}
 P = 4  # bytes per float (FP32 workload)
 # sources that define the gather-push-deposit kernel (its traffic summary is
 # valid only for them)
@@ -197,13 +208,21 @@ def run_gpu(args):
     timer_stats["gpd_ms_timer_on"] = float(np.median(on_ms))
     timer_stats["gpd_ms_timer_off"] = float(np.median(off_ms))
     timer_stats["overhead"] = float(np.median(on_ms) / np.median(off_ms) - 1.0)
+    # the unstaged reference: every particle gathers from and deposits into
+    # global memory directly (no LDS windows), same launch mode
+    ctx.set_staging(False)
+    un_step, un_k, un_n = timed(mode, False, nsteps, 2, True)
+    ctx.set_staging(True)
+    ctx.slow_path_count()
+    unstaged = {"ms_per_step": un_step, "gpd_ms": un_k[0] / max(1, un_n[0]),
+                "staged_speedup": (un_k[0] / max(1, un_n[0])) / gpd_ms}
     ctx.finalize()
     return {
         "n_p": n_p, "ms_per_step": best_ms, "ms_eager_events": ms_step, "ms_graph": ms_graph,
         "gpd_ms": gpd_ms, "gpd_launches_per_step": float(kn[0]) / args.steps,
         "yee_ms": kms[1] / max(1, kn[1]), "sort_ms_total": kms[2], "gpd_bytes": gpd_bytes,
         "step_bytes": step_bytes, "modes_ms": extra, "tuning": tun.as_dict(), "slow_path": slow,
-        "timer_costs": timer_stats,
+        "timer_costs": timer_stats, "unstaged": unstaged,
     }
 
 
@@ -533,6 +552,12 @@ def main():
         "ms_graph": r["ms_graph"], "ms_eager": r["ms_eager_events"],
         "yee_ms": r["yee_ms"], "slow_path_particles": r["slow_path"],
         "timer_costs": r["timer_costs"],
+        "unstaged_reference_kernel": r["unstaged"],
+        # the same kernel against the vector-ALU peak
+        "alu": {"bound": "alu", "flops_per_particle_step": FLOPS_PER_PARTICLE_STEP[2],
+                "achieved": r["n_p"] * FLOPS_PER_PARTICLE_STEP[2] / (r["gpd_ms"] * 1e-3) / 1e12,
+                "peak": FP32_VECTOR_PEAK_TFS, "peak_packed": FP32_PACKED_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": r["n_p"] * FLOPS_PER_PARTICLE_STEP[2] / (r["gpd_ms"] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFS},
     }
     if not args.no_c3:
         out["uneven_boxes"] = uneven_boxes()

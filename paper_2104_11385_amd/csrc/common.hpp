@@ -79,6 +79,7 @@ struct GpdArgs {
     int *jdirty;                   // [n[2]] set to 1 for every z-plane of J written
     int mode;
     int timer;                 // nonzero: per-box clock counters are updated
+    int staged;                // zero: no LDS windows, every particle on the global path
     int tile_base;             // PER_BOX: first tile of the box
     int species_only;          // PER_BOX: species of this launch
     const int4 *queue;         // PERSISTENT: (tile, begin, end, -)

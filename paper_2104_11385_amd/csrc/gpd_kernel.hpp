@@ -489,7 +489,7 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
     const int T[3] = {TX, TY, TZ};
     const int org[3] = {td.x0, td.y0, td.z0};
     int rel[3];
-    bool fast = true;
+    bool fast = A.staged != 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         rel[d] = wrap_rel(ref[d] - org[d], H, A.n[d]);
@@ -771,9 +771,8 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
         const TileDesc td = A.tiles[tile];
 
         // stage E and B of the tile window (one index computation serves the
-        // six components; windows inside the domain need no wrap); clear the
-        // J window
-        {
+        // six components; windows inside the domain need no wrap)
+        if (A.staged) {
             const int ox = td.x0 - H - C::RL_EB, oy = td.y0 - H - C::RL_EB, oz = td.z0 - H - C::RL_EB;
             const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::EX <= A.n[0] && oy + C::EY <= A.n[1] &&
                                 oz + C::EZ <= A.n[2];
@@ -887,7 +886,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
         __syncthreads();
 
         // flush the J window (nonzero entries only)
-        {
+        if (A.staged) {
             const int ox = td.x0 - H - C::RL_J, oy = td.y0 - H - C::RL_J, oz = td.z0 - H - C::RL_J;
             const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::JX <= A.n[0] && oy + C::JY <= A.n[1] &&
                                 oz + C::JZ <= A.n[2];
@@ -992,6 +991,7 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
     A.jdirty = L.jdirty;
     A.mode = L.mode;
     A.timer = L.timer;
+    A.staged = L.staged;
     A.tile_base = L.tile_base;
     A.species_only = L.species_only;
     A.queue = L.queue;

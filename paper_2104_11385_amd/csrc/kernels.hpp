@@ -79,6 +79,7 @@ struct GpdLaunch {
     int *jdirty;               // [nz] z-planes of J the deposit touched
     int mode;
     int timer;
+    int staged;
     int tile_base;
     int species_only;
     const int4 *queue;

@@ -224,6 +224,7 @@ GpdLaunch pic_ctx::gpd_args() const {
     L.jdirty = d_jdirty[jcur];
     L.mode = mode;
     L.timer = cost_timer ? 1 : 0;
+    L.staged = staged ? 1 : 0;
     L.tile_base = 0;
     L.species_only = -1;
     L.queue = Q.queue;
@@ -1175,6 +1176,18 @@ PIC_API int pic_set_cost_timer(pic_ctx *ctx, int32_t enable) {
         hipError_t e = hipStreamSynchronize(ctx->st);
         if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamSynchronize");
         ctx->cost_timer = on;
+        ctx->drop_graphs();
+    }
+    return PIC_OK;
+}
+
+PIC_API int pic_set_staging(pic_ctx *ctx, int32_t enable) {
+    CHECK_CTX(ctx);
+    bool on = enable != 0;
+    if (on != ctx->staged) {
+        hipError_t e = hipStreamSynchronize(ctx->st);
+        if (e != hipSuccess) return ctx->hip_fail(e, "hipStreamSynchronize");
+        ctx->staged = on;
         ctx->drop_graphs();
     }
     return PIC_OK;

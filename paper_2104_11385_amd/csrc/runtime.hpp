@@ -88,6 +88,7 @@ struct pic_ctx {
     // timing
     bool timing = false;
     bool cost_timer = true;  // per-box clock counters in the gather-push-deposit kernel
+    bool staged = true;      // tile windows staged in LDS (off: global-memory reference path)
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events[4];
     std::pair<hipEvent_t, hipEvent_t> ev_pending{};
     int ev_kind = 0;

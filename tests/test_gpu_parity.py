@@ -125,6 +125,23 @@ def test_dense_nodes_both_particle_orders(precision, order, run_sum):
     compare(ctx, wl, x, u, w, sp, ids, F, 10, TOL[precision])
 
 
+@pytest.mark.parametrize("precision,order", [(8, 2), (4, 2), (8, 1), (4, 3)])
+def test_unstaged_reference_path(precision, order):
+    # no LDS windows: every particle gathers from and deposits into the
+    # global arrays; the same oracle bar applies
+    wl = quad_workload(precision, seed=17)
+    wl.order = order
+    print(f"[parity] unstaged precision={precision} order={order}", flush=True)
+    ctx = make_ctx(wl, load=False)
+    ctx.set_staging(False)
+    F0 = picsynth.random_fields(wl.n, 5, amp=0.03)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+    ctx.slow_path_count()
+    ctx.step(6)
+    assert ctx.slow_path_count() == 6 * len(ids)
+    compare(ctx, wl, x, u, w, sp, ids, F, 6, TOL[precision])
+
+
 def test_sort_interval_and_tiles_do_not_change_results():
     wl = quad_workload(8, seed=12)
     res = []
