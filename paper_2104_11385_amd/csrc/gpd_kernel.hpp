@@ -18,6 +18,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <type_traits>
 
 namespace pb {
@@ -818,20 +819,36 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
         unsigned nslow = 0;
         const int lane = tid & 63, qslot0 = tid & ~63;
         int qn = 0;  // entries in this wave's queue (wave-uniform)
-        for (int s = 0; s < nsp; ++s) {
-            if (A.mode == MODE_PER_BOX && s != A.species_only) continue;
-            int sb = max(pbeg, A.segstart[tile * nsp + s]);
-            int se = min(pend, A.segstart[tile * nsp + s + 1]);
-            real hq = A.h[s], cq = A.coefq[s];
-            // the next particle's loads are issued before this one is computed;
-            // the trip count is the same for every lane of the block
+        {
+            // The item's particles, all species together: wave w takes the
+            // runs of 64 particles w, w + W, w + 2W, ... (W waves), so that
+            // only the item's last run is partly filled and no wave steps
+            // through empty runs.  A particle's species follows from the
+            // segment bounds inside the tile.
+            const int sb = pbeg, se = pend;
+            int bnd[kMaxSpecies - 1];  // first particle of species k + 1
+#pragma unroll
+            for (int k = 0; k < kMaxSpecies - 1; ++k)
+                bnd[k] = k + 1 < nsp ? A.segstart[tile * nsp + k + 1] : INT_MAX;
+            // the next particle's loads are issued before this one is
+            // computed; the trip count is the same for every lane of a wave
             PState<real> cur;
             if (sb + tid < se) cur.load(A.P, sb + tid);
             cur.settle();
-            for (int base = sb; base < se; base += nthr) {
-                const int p = base + tid;
+            for (int base = sb + (tid & ~63); base < se; base += nthr) {
+                const int p = base + lane;
                 PState<real> nxt;
                 if (p + nthr < se) nxt.load(A.P, p + nthr);
+                int sp = 0;
+#pragma unroll
+                for (int k = 0; k < kMaxSpecies - 1; ++k) sp += p >= bnd[k];
+                real hq = A.h[0], cq = A.coefq[0];
+#pragma unroll
+                for (int k = 1; k < kMaxSpecies; ++k)
+                    if (sp == k) {
+                        hq = A.h[k];
+                        cq = A.coefq[k];
+                    }
                 Deferred<real> df;
                 df.want = false;
                 df.keep = false;
