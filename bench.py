@@ -210,12 +210,14 @@ def run_gpu(args):
     timer_stats["overhead"] = float(np.median(on_ms) / np.median(off_ms) - 1.0)
     # the unstaged reference: every particle gathers from and deposits into
     # global memory directly (no LDS windows), same launch mode
-    ctx.set_staging(False)
-    un_step, un_k, un_n = timed(mode, False, nsteps, 2, True)
-    ctx.set_staging(True)
-    ctx.slow_path_count()
-    unstaged = {"ms_per_step": un_step, "gpd_ms": un_k[0] / max(1, un_n[0]),
-                "staged_speedup": (un_k[0] / max(1, un_n[0])) / gpd_ms}
+    unstaged = None
+    if not args.no_unstaged:
+        ctx.set_staging(False)
+        un_step, un_k, un_n = timed(mode, False, nsteps, 2, True)
+        ctx.set_staging(True)
+        ctx.slow_path_count()
+        unstaged = {"ms_per_step": un_step, "gpd_ms": un_k[0] / max(1, un_n[0]),
+                    "staged_speedup": (un_k[0] / max(1, un_n[0])) / gpd_ms}
     ctx.finalize()
     return {
         "n_p": n_p, "ms_per_step": best_ms, "ms_eager_events": ms_step, "ms_graph": ms_graph,
@@ -511,6 +513,8 @@ def main():
     ap.add_argument("--no-lb", action="store_true", help="skip the load-balancing study")
     ap.add_argument("--no-calibrate", action="store_true", help="skip the heuristic-weight calibration runs")
     ap.add_argument("--no-c3", action="store_true", help="skip the uneven-box (4096 mixed boxes) comparison")
+    ap.add_argument("--no-unstaged", action="store_true",
+                    help="skip the unstaged reference kernel (keeps kernel profiles to the staged kernel)")
     ap.add_argument("--lb-steps", type=int, default=300)
     ap.add_argument("--lb-edges", action="store_true", help="also sweep the balancing study's box edge (16..128)")
     args = ap.parse_args()
