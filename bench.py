@@ -38,7 +38,9 @@ FP32_PACKED_PEAK_TFS = 2 * FP32_VECTOR_PEAK_TFS
 # FMA counting 2 and the shape factors shared between gather and deposit):
 # gather 444 (weights 51, six staggered components 390, external B 3),
 # Boris rotation 66, move 12, Esirkepov deposit 229.
-FLOPS_PER_PARTICLE_STEP = {2: 751}
+# Cubic shapes: gather 972 (weights 87, components 882, external B 3),
+# Boris rotation 66, move 15, Esirkepov deposit 528.
+FLOPS_PER_PARTICLE_STEP = {2: 751, 3: 1581}
 P = 4  # bytes per float (FP32 workload)
 # sources that define the gather-push-deposit kernel (its traffic summary is
 # valid only for them)
@@ -226,6 +228,41 @@ def run_gpu(args):
         "step_bytes": step_bytes, "modes_ms": extra, "tuning": tun.as_dict(), "slow_path": slow,
         "timer_costs": timer_stats, "unstaged": unstaged,
     }
+
+
+def cubic_order(steps=40, warmup=5):
+    """The benchmark workload with cubic shapes (the paper's own order):
+    step time, particle kernel time and its vector-ALU fraction, with the
+    kept-node currents summed across lanes and without."""
+    from paper_2104_11385_amd import picbal as pb
+    wl = workload()
+    wl.order = 3
+    ctx = make_ctx(wl)
+    import picsynth
+    n_p = int(sum(picsynth.species_count(wl, s) for s in range(len(wl.species))))
+    out = {"workload": "256^3, 64 boxes of 64^3, the slab plasma of the benchmark (27,262,976 particles), "
+                       "cubic shapes, FP32", "tuning": ctx.get_tuning().as_dict()}
+    for rs in (1, 0):
+        ctx.set_tuning(run_sum=rs)
+        ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, True)
+        ctx.step(warmup)
+        ctx.sync()
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        ctx.sync()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, False)
+        ctx.kernel_timing(True)
+        k0, n0 = ctx.kernel_times()
+        ctx.step(10)
+        k1, n1 = ctx.kernel_times()
+        ctx.kernel_timing(False)
+        gpd_ms = (k1[0] - k0[0]) / max(1, n1[0] - n0[0])
+        tf = n_p * FLOPS_PER_PARTICLE_STEP[3] / (gpd_ms * 1e-3) / 1e12
+        out[f"run_sum{rs}"] = {"ms_per_step": ms, "particle_steps_per_s": n_p / (ms * 1e-3), "gpd_ms": gpd_ms,
+                               "alu_tflops": tf, "alu_frac": tf / FP32_VECTOR_PEAK_TFS}
+    ctx.finalize()
+    return out
 
 
 def cpu_baseline(sample_particles=3_000_000):
@@ -565,6 +602,8 @@ def main():
     }
     if not args.no_c3:
         out["uneven_boxes"] = uneven_boxes()
+    if not args.quick:
+        out["cubic_shapes"] = cubic_order()
     weights = None
     if not args.no_calibrate:
         from paper_2104_11385_amd import calibrate
