@@ -111,7 +111,12 @@ typedef struct {
 /* Kernel tuning.  Tile edges must be one of the compiled shapes (8x8x8,
  * 8x8x4, 8x4x4, 4x4x4) and divide every box edge; halo is the number of
  * cells a particle may drift outside its tile between sorts and still use the
- * staged fields (particles beyond it take a slower global-memory path). */
+ * staged fields (particles beyond it take a slower global-memory path).
+ * pic_init's default: the first of 8x4x4, 4x4x4, 8x8x4, 8x8x8 that divides
+ * every box edge and whose LDS windows let three 256-thread blocks share a
+ * CU (else two, else one); block 256, chunk 4096, sort_interval 20,
+ * blocks_per_cu = the number of blocks whose LDS fits on a CU (1..4),
+ * run_sum 1. */
 typedef struct {
     int32_t tile[3];
     int32_t halo;          /* 1 */
