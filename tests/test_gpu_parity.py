@@ -142,6 +142,31 @@ def test_unstaged_reference_path(precision, order):
     compare(ctx, wl, x, u, w, sp, ids, F, 6, TOL[precision])
 
 
+@pytest.mark.parametrize("precision", [8, 4])
+def test_four_species_in_shared_waves(precision):
+    # four species with different charge-to-mass ratios: the particle loop
+    # runs over a tile's species together, so waves hold particles of
+    # several species and each lane takes its own q/m
+    n = (16, 8, 16)
+    N0 = picsynth.N0_DEFAULT
+    sp = [picsynth.Species("electrons", -1.0, 1.0, N0, ppc=3, region_lo=(0, 0, 2), region_hi=(16, 8, 14),
+                           u_th=(0.03,) * 3),
+          picsynth.Species("positrons", 1.0, 1.0, N0, ppc=2, region_lo=(0, 0, 4), region_hi=(16, 8, 12),
+                           u_th=(0.03,) * 3, u_drift=(0.0, 0.0, 0.02)),
+          picsynth.Species("protons", 1.0, 1836.0, N0, ppc=2, region_lo=(0, 0, 2), region_hi=(16, 8, 14),
+                           u_th=(0.001,) * 3),
+          picsynth.Species("alphas", 2.0, 7294.0, N0, ppc=1, region_lo=(0, 0, 6), region_hi=(16, 8, 10),
+                           u_th=(0.001,) * 3)]
+    wl = picsynth.Workload("four", n, picsynth.uniform_boxes(n, 8), sp, dt=0.5, order=2, precision=precision,
+                           seed=23)
+    print(f"[parity] four species precision={precision}", flush=True)
+    ctx = make_ctx(wl, load=False)
+    F0 = picsynth.random_fields(wl.n, 19, amp=0.04)
+    x, u, w, ids, sp_, F = set_state(ctx, wl, F0)
+    ctx.step(8)
+    compare(ctx, wl, x, u, w, sp_, ids, F, 8, TOL[precision])
+
+
 def test_sort_interval_and_tiles_do_not_change_results():
     wl = quad_workload(8, seed=12)
     res = []
