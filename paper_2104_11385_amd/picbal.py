@@ -135,12 +135,11 @@ def _check(rc, ctx=None):
 
 
 def boxes_array(boxes) -> ctypes.Array:
-    boxes = np.asarray(boxes, dtype=np.int32).reshape(-1, 6)
-    arr = (pic_box * len(boxes))()
-    for b, row in enumerate(boxes):
-        arr[b].lo[:] = [int(v) for v in row[:3]]
-        arr[b].hi[:] = [int(v) for v in row[3:]]
-    return arr
+    # pic_box is six int32 (lo[3], hi[3]): a C-contiguous [n, 6] int32 array
+    # has the same layout, so the ctypes array is a view of a private copy
+    boxes = np.array(boxes, dtype=np.int32, order="C", copy=True).reshape(-1, 6)
+    assert ctypes.sizeof(pic_box) == 24
+    return (pic_box * len(boxes)).from_buffer(boxes)
 
 
 # ---------------------------------------------------------------------------
