@@ -852,6 +852,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 Deferred<real> df;
                 df.want = false;
                 df.keep = false;
+                df.rel = 0x080808;  // the tile origin, for lanes without a particle
                 PState<real> moved;
                 if (p < se)
                     push_particle<real, M, TX, TY, TZ, H, R>(A, p, cur, td, hq, cq, sEB, sJ, nslow, df, moved);
