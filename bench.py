@@ -346,6 +346,8 @@ def uneven_boxes(steps=5, warmup=2):
     step_bytes = n_p * 13 * P + int(np.prod(wl.n)) * 15 * P + occ * 9 * P
     res["algorithmic_bytes_per_step"] = step_bytes
     res["step_hbm_frac"] = step_bytes / (res["persistent"]["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+    for name in ("persistent", "per_box"):
+        res[name]["step_hbm_frac"] = step_bytes / (res[name]["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     ctx.finalize()
     return res
 
@@ -590,6 +592,8 @@ def main():
                      "measured_copy_peak": copy_gbs, "frac_of_copy_peak": gpd_gbs / copy_gbs},
         "step_hbm_frac": r["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "modes_ms_per_step": r["modes_ms"],
+        "modes_step_hbm_frac": {k: (r["step_bytes"] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS if v else None)
+                                for k, v in r["modes_ms"].items()},
         "ms_graph": r["ms_graph"], "ms_eager": r["ms_eager_events"],
         "yee_ms": r["yee_ms"], "slow_path_particles": r["slow_path"],
         "timer_costs": r["timer_costs"],
