@@ -11,6 +11,15 @@
 // Per-box costs follow Sec. 2.2 and Fig. 2a: a device clock is read around
 // the compute-intensive work, summed on chip, then added once per block to a
 // global per-box counter.
+//
+// Structure: a block takes a work item (a tile's particles, all species),
+// stages the tile's E/B window in LDS and accumulates J in an FP64 LDS
+// window that it adds to the global J at the end of the item.  Each wave
+// walks its own 64-particle runs of the item.  With R (node-major particle
+// order), the currents of lanes whose particles keep a common reference node
+// are summed across the lanes of each 16-lane row before one LDS add per
+// run; particles that change node wait in a per-wave queue for a wider
+// deposit on full waves.
 #pragma once
 
 #include "device_util.hpp"
