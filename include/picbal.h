@@ -200,6 +200,14 @@ PIC_API int pic_box_counts(pic_ctx *ctx, int64_t *counts);
 
 /* ---- state access ------------------------------------------------------ */
 
+/* Looks up n particles of species s by id (n <= 2^24, ids distinct) without
+ * copying the whole species: x3[n][3] and u3[n][3] (caller-owned) receive
+ * each particle's position (cell units, as pic_get_particles) and momentum,
+ * found[n] 1 or 0 (then x3 and u3 hold zeros).  Allocates and frees device
+ * scratch; synchronises.  PIC_EINVAL for a repeated id. */
+PIC_API int pic_get_particles_by_id(pic_ctx *ctx, int32_t species, const int64_t *ids, int64_t n, double *x3,
+                                    double *u3, int32_t *found);
+
 /* Copies species s's particles to caller arrays sized by *n_inout; on return
  * *n_inout is the particle count (PIC_ECAPACITY if the arrays are too small;
  * the count is still written).  Order is unspecified; ids identify

@@ -120,6 +120,8 @@ struct YeeBuffers {
 };
 hipError_t launch_yee_half(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
 hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
+hipError_t launch_find_ids(int prec, const ParticlesRaw &P, int np, int s, const int64_t *q, int n, uint32_t *cell,
+                           void *f, void *u, int *found, hipStream_t st);
 hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,
                              hipStream_t st);
 hipError_t launch_features(int prec, const ParticlesRaw &P, int np, const Geom &G, int nb, const int *box_hi,

@@ -706,6 +706,43 @@ hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, 
     return hipGetLastError();
 }
 
+// Particles of species s whose ids are in the ascending list q[0, n): each
+// found particle's cell, offsets and momentum go to slot k of the outputs,
+// k its id's position in q, and found[k] is set.
+template <typename real>
+__global__ void k_find_ids(Particles<real> P, int np, int s, const int64_t *q, int n, uint32_t *cell, real *f,
+                           real *u, int *found) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np || P.sp[p] != s) return;
+    const int64_t id = P.id[p];
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (q[mid] < id) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo >= n || q[lo] != id) return;
+    cell[lo] = P.cell[p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        f[3 * lo + d] = P.f[d][p];
+        u[3 * lo + d] = P.u[d][p];
+    }
+    found[lo] = 1;
+}
+
+hipError_t launch_find_ids(int prec, const ParticlesRaw &P, int np, int s, const int64_t *q, int n, uint32_t *cell,
+                           void *f, void *u, int *found, hipStream_t st) {
+    if (np <= 0 || n <= 0) return hipSuccess;
+    if (prec == 8)
+        k_find_ids<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(P), np, s, q, n, cell, (double *)f,
+                                                           (double *)u, found);
+    else
+        k_find_ids<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(P), np, s, q, n, cell, (float *)f, (float *)u,
+                                                         found);
+    return hipGetLastError();
+}
+
 hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,
                              hipStream_t st) {
     if (np <= 0) return hipSuccess;

@@ -1060,6 +1060,67 @@ PIC_API int pic_get_particles(pic_ctx *ctx, int32_t species, double *x3, double 
     return k > cap_out ? PIC_ECAPACITY : PIC_OK;
 }
 
+PIC_API int pic_get_particles_by_id(pic_ctx *ctx, int32_t species, const int64_t *ids, int64_t n, double *x3,
+                                    double *u3, int32_t *found) {
+    CHECK_CTX(ctx);
+    if (species < 0 || species >= ctx->nsp || n < 0 || n > (int64_t)1 << 24 ||
+        (n > 0 && (!ids || !x3 || !u3 || !found)))
+        return ctx->fail(PIC_EINVAL, "bad species, count (0..2^24) or null arrays");
+    if (n == 0) return PIC_OK;
+    std::vector<int64_t> order(n), q(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return ids[a] < ids[b]; });
+    for (int64_t k = 0; k < n; ++k) q[k] = ids[order[k]];
+    for (int64_t k = 1; k < n; ++k)
+        if (q[k] == q[k - 1]) return ctx->fail(PIC_EINVAL, "repeated id");
+    const size_t P = (size_t)ctx->prec;
+    void *dq = nullptr, *dcell = nullptr, *df = nullptr, *du = nullptr, *dfound = nullptr;
+    auto release = [&]() {
+        for (void *b : {dq, dcell, df, du, dfound})
+            if (b) (void)hipFree(b);
+    };
+    hipError_t e = hipMalloc(&dq, 8 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&dcell, 4 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&df, 3 * P * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&du, 3 * P * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&dfound, 4 * (size_t)n);
+    if (e != hipSuccess) {
+        release();
+        (void)hipGetLastError();
+        return ctx->fail(PIC_ENOMEM, "no device memory for the id lookup");
+    }
+    e = hipMemcpyAsync(dq, q.data(), 8 * (size_t)n, hipMemcpyHostToDevice, ctx->st);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)dfound, (size_t)n, ctx->st);
+    if (e == hipSuccess)
+        e = launch_find_ids(ctx->prec, ctx->P[ctx->pcur], (int)ctx->np, species, (const int64_t *)dq, (int)n,
+                            (uint32_t *)dcell, df, du, (int *)dfound, ctx->st);
+    std::vector<uint32_t> cell(n);
+    std::vector<int32_t> fnd(n);
+    std::vector<unsigned char> fb(3 * P * (size_t)n), ub(3 * P * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpyAsync(cell.data(), dcell, 4 * (size_t)n, hipMemcpyDeviceToHost, ctx->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(fnd.data(), dfound, 4 * (size_t)n, hipMemcpyDeviceToHost, ctx->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(fb.data(), df, fb.size(), hipMemcpyDeviceToHost, ctx->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ub.data(), du, ub.size(), hipMemcpyDeviceToHost, ctx->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+    release();
+    if (e != hipSuccess) return ctx->hip_fail(e, "id lookup");
+    auto val = [&](const std::vector<unsigned char> &b, size_t i) -> double {
+        if (P == 8) return ((const double *)b.data())[i];
+        return (double)((const float *)b.data())[i];
+    };
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t o = order[k];
+        found[o] = fnd[k];
+        int c[3];
+        unpack_cell(cell[k], c[0], c[1], c[2]);
+        for (int d = 0; d < 3; ++d) {
+            x3[3 * o + d] = fnd[k] ? (double)c[d] + val(fb, 3 * (size_t)k + d) : 0.0;
+            u3[3 * o + d] = fnd[k] ? val(ub, 3 * (size_t)k + d) : 0.0;
+        }
+    }
+    return PIC_OK;
+}
+
 PIC_API int pic_set_particles(pic_ctx *ctx, int32_t species, const double *x3, const double *u3, const double *w,
                               const int64_t *id, int64_t n) {
     CHECK_CTX(ctx);

@@ -97,6 +97,7 @@ def lib():
             "pic_mlp_get_weights": (ctypes.c_int, [P, P, i64]),
             "pic_set_cost_timer": (ctypes.c_int, [P, i32]),
             "pic_set_staging": (ctypes.c_int, [P, i32]),
+            "pic_get_particles_by_id": (ctypes.c_int, [P, i32, P, i64, P, P, P]),
             "pic_kernel_timing": (ctypes.c_int, [P, i32]),
             "pic_kernel_times": (ctypes.c_int, [P, P, P]),
             "pic_slow_path_count": (ctypes.c_int, [P, P]),
@@ -117,7 +118,7 @@ def exported_symbols():
             "pic_get_particles", "pic_set_particles", "pic_get_field", "pic_set_field", "lb_distribute",
             "lb_efficiency", "lb_should_adopt", "lb_morton_key", "lb_comm_volume", "pic_box_features", "pic_mlp_nparam",
             "pic_mlp_train", "pic_mlp_predict", "pic_mlp_loss_grad", "pic_mlp_set_weights",
-            "pic_mlp_get_weights", "pic_set_cost_timer", "pic_set_staging", "pic_kernel_timing", "pic_kernel_times", "pic_slow_path_count",
+            "pic_mlp_get_weights", "pic_set_cost_timer", "pic_set_staging", "pic_get_particles_by_id", "pic_kernel_timing", "pic_kernel_times", "pic_slow_path_count",
             "pic_strerror", "pic_last_error"]
 
 
@@ -335,6 +336,14 @@ class PicContext:
 
     def set_cost_timer(self, enable=True):
         self._c(lib().pic_set_cost_timer(self.h, 1 if enable else 0))
+
+    def get_particles_by_id(self, species, ids):
+        """(x [n,3], u [n,3], found bool[n]) of the given ids of one species."""
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        n = len(ids)
+        x = np.zeros((n, 3)); u = np.zeros((n, 3)); found = np.zeros(n, dtype=np.int32)
+        self._c(lib().pic_get_particles_by_id(self.h, int(species), _ptr(ids), n, _ptr(x), _ptr(u), _ptr(found)))
+        return x, u, found.astype(bool)
 
     def set_staging(self, enable=True):
         self._c(lib().pic_set_staging(self.h, 1 if enable else 0))

@@ -1,6 +1,9 @@
-"""Parity at the benchmark's full size, in the launch configuration the
-benchmark times (256^3 cells, 64 boxes of 64^3, 27,262,976 particles, FP32,
-quadratic shapes, persistent kernel with graph replay).
+"""Parity at full size, in the launch configuration the benchmark times
+(persistent kernel with graph replay): the benchmark workload (256^3 cells,
+64 boxes of 64^3, 27,262,976 particles, FP32, quadratic shapes), and the
+uneven-box (512^3, 4096 mixed boxes, 1.13e9 particles) and balancing-study
+(384x384x768, 3456 boxes, 94,371,840 particles) workloads from their own
+initial state.
 
 The oracle cannot step 27 M particles in a test, so it is checked on samples
 it can compute one by one:
@@ -114,3 +117,115 @@ def test_c2_one_step_sampled_against_oracle():
         scale = max(np.abs(want).max(), np.abs(F0[comp]).max(), 1e-30)
         err = np.abs(got - want).max()
         assert err <= TOL * scale, f"component {comp}: max error {err:.3e} against scale {scale:.3e}"
+
+
+def _ids_of_cells(wl, s, cells):
+    """Ids of species s whose initial cell is one of `cells` ([k, 3])."""
+    sp = wl.species[s]
+    cells = np.asarray(cells, dtype=np.int64).reshape(-1, 3)
+    if sp.box_ppc is None:
+        lo = np.array(sp.region_lo)
+        hi = np.array(sp.region_hi if sp.region_hi is not None else wl.n)
+        ext = hi - lo
+        inside = np.all((cells >= lo) & (cells < hi), axis=1)
+        g = cells[inside] - lo
+        rank = g[:, 0] + ext[0] * (g[:, 1] + ext[1] * g[:, 2])
+        return (rank[:, None] * sp.ppc + np.arange(sp.ppc)[None, :]).ravel()
+    b = wl.boxes.astype(np.int64)
+    ext = b[:, 3:] - b[:, :3]
+    base = np.concatenate([[0], np.cumsum(ext.prod(axis=1) * sp.box_ppc)])
+    out = []
+    for c in cells:
+        bi = int(np.nonzero(np.all((c >= b[:, :3]) & (c < b[:, 3:]), axis=1))[0][0])
+        ppc = int(sp.box_ppc[bi])
+        if ppc == 0:
+            continue
+        l = c - b[bi, :3]
+        local = l[0] + ext[bi, 0] * (l[1] + ext[bi, 1] * l[2])
+        out.append(base[bi] + local * ppc + np.arange(ppc))
+    return np.concatenate(out) if out else np.zeros(0, np.int64)
+
+
+def _neighbourhood(wl, s, cells):
+    n = np.array(wl.n)
+    r = np.arange(-REACH, REACH + 1)
+    allc = []
+    for c in cells:
+        gx, gy, gz = np.meshgrid((c[0] + r) % n[0], (c[1] + r) % n[1], (c[2] + r) % n[2], indexing="ij")
+        allc.append(np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1))
+    return np.unique(_ids_of_cells(wl, s, np.concatenate(allc)))
+
+
+def _sampled_one_step(name, cells, nsample=2000, seed=5):
+    """One step of workload `name` from its initial state on the device,
+    checked on sampled particles (looked up by id) and at sampled cells."""
+    import bench
+    import oracle
+    from paper_2104_11385_amd import picbal as pb
+
+    wl = picsynth.config(name)
+    n = tuple(wl.n)
+    print(f"full-size parity: {name}, persistent + graph, 1 step", flush=True)
+    rng = np.random.default_rng(seed)
+    samples = [np.sort(rng.choice(picsynth.species_count(wl, s), nsample, replace=False))
+               for s in range(len(wl.species))]
+    ctx = bench.ctx_for(wl)
+    try:
+        ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, True)
+        ctx.step(1)
+        ctx.sync()
+        cz = np.array([c[2] for c in cells]); cy = np.array([c[1] for c in cells]); cx = np.array([c[0] for c in cells])
+        got_cells = np.stack([ctx.get_field(c)[cz, cy, cx] for c in range(9)])
+        got = [ctx.get_particles_by_id(s, samples[s]) for s in range(len(wl.species))]
+    finally:
+        ctx.finalize()
+
+    xs, us, ws, sps, idl = [], [], [], [], []
+    for s in range(len(wl.species)):
+        ids = np.union1d(samples[s], _neighbourhood(wl, s, cells))
+        x, u, w, i = picsynth.particles(wl, s, ids)
+        xs.append(x); us.append(u); ws.append(w); sps.append(np.full(len(w), s, np.int32)); idl.append(i)
+    x = np.ascontiguousarray(np.concatenate(xs)); u = np.ascontiguousarray(np.concatenate(us))
+    w = np.concatenate(ws); sp = np.concatenate(sps)
+    q = np.array([s.charge for s in wl.species]); mass = np.array([s.mass for s in wl.species])
+    F = np.ascontiguousarray(picsynth.initial_fields(wl))
+    oracle.pic_step(wl.order, n, wl.dt, x, u, w, sp, q, mass, F, 1)
+
+    off = 0
+    for s in range(len(wl.species)):
+        gx, gu, found = got[s]
+        assert found.all(), f"species {s}: {int((~found).sum())} sampled ids not found"
+        k = np.searchsorted(idl[s], samples[s])
+        ox, ou = x[off + k], u[off + k]
+        d = np.abs(gx - ox)
+        d = np.minimum(d, np.array(n) - d)
+        assert d.max() <= TOL, f"species {s}: max |dx| = {d.max():.3e}"
+        scale = max(np.abs(ou).max(), 1e-30)
+        assert np.abs(gu - ou).max() <= TOL * scale, f"species {s}: max |du| = {np.abs(gu - ou).max():.3e}"
+        off += len(idl[s])
+    want_cells = F[:, cz, cy, cx]
+    for comp in range(9):
+        scale = max(np.abs(want_cells[comp]).max(), 1e-30)
+        err = np.abs(got_cells[comp] - want_cells[comp]).max()
+        assert err <= TOL * scale, f"component {comp}: max error {err:.3e} against scale {scale:.3e}"
+    # the sampled cells carry current: the check is not vacuous
+    assert np.abs(want_cells[6:9]).max() > 0
+
+
+def test_mixed_boxes_one_step_sampled_against_oracle():
+    # 512^3, 4096 boxes of 64^3 / 32^3 / 16^3 with lognormal ppc up to 64
+    rng = np.random.default_rng(8)
+    cells = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(12)]
+    # faces of boxes of each size and of the domain
+    cells += [(64, 10, 20), (63, 10, 20), (96, 64, 32), (80, 80, 79), (16, 16, 16), (511, 0, 255),
+              (0, 511, 128), (255, 256, 511), (128, 130, 64), (47, 48, 49)]
+    _sampled_one_step("c3", cells)
+
+
+def test_balancing_study_one_step_sampled_against_oracle():
+    # 384 x 384 x 768, 3456 boxes of 32^3, two drifting species in z [374, 394)
+    rng = np.random.default_rng(9)
+    cells = [(int(rng.integers(0, 384)), int(rng.integers(0, 384)), int(rng.integers(374, 394))) for _ in range(14)]
+    cells += [(0, 0, 384), (383, 100, 383), (31, 32, 374), (32, 31, 393), (200, 383, 373), (5, 6, 394),
+              (160, 160, 384), (64, 95, 375)]
+    _sampled_one_step("c4", cells)

@@ -233,9 +233,30 @@ def test_box_counts_after_steps(precision):
 
 
 @pytest.mark.parametrize("precision", [8, 4])
-def test_device_loader_matches_generator(precision):
-    # pic_init's on-device Philox loader against the host generator
+@pytest.mark.parametrize("per_box", [False, True])
+def test_device_loader_matches_generator(precision, per_box):
+    # pic_init's on-device Philox loader against the host generator: a
+    # loading region at fixed ppc, or a ppc per box (mixed box sizes)
     wl = quad_workload(precision, seed=77)
+    if per_box:
+        n = (32, 32, 32)
+        boxes = []
+        for bz in range(2):
+            for by in range(2):
+                for bx in range(2):
+                    o = np.array([bx, by, bz]) * 16
+                    if (bx + by + bz) % 2:
+                        boxes.append([*o, *(o + 16)])
+                    else:
+                        for k in range(8):
+                            q = o + 8 * np.array([k & 1, (k >> 1) & 1, k >> 2])
+                            boxes.append([*q, *(q + 8)])
+        boxes = np.array(boxes, dtype=np.int32)
+        ppc = picsynth.lognormal_box_ppc(len(boxes), 41, cap=6)
+        sp = [picsynth.Species("electrons", -1.0, 1.0, picsynth.N0_DEFAULT, box_ppc=ppc, u_th=(0.01,) * 3),
+              picsynth.Species("protons", 1.0, 1836.0, picsynth.N0_DEFAULT, box_ppc=ppc[::-1].copy(),
+                               u_th=(0.001,) * 3)]
+        wl = picsynth.Workload("per-box", n, boxes, sp, dt=0.5, order=2, precision=precision, seed=78)
     ctx = make_ctx(wl, load=True)
     for s in range(2):
         gx, gu, gw, gi = ctx.get_particles(s)
@@ -272,3 +293,20 @@ def test_autotune_keeps_state_and_picks_a_valid_tuning(mode):
     set_state(ctx2, wl, F0)
     t2, ms2 = ctx2.autotune(2)
     assert ms2 == -1.0 and tuple(t2.tile) == tuple(t.tile)
+
+
+def test_particles_by_id_match_full_copy():
+    pb = _pb()
+    wl = quad_workload(4, seed=29)
+    ctx = make_ctx(wl, load=True)
+    ctx.step(2)
+    gx, gu, gw, gi = ctx.get_particles(1)
+    rng = np.random.default_rng(3)
+    pick = rng.choice(len(gi), 300, replace=False)
+    ids = np.concatenate([gi[pick], [10 ** 12]])       # the last id does not exist
+    x, u, found = ctx.get_particles_by_id(1, ids)
+    assert found[:-1].all() and not found[-1]
+    np.testing.assert_array_equal(x[:-1], gx[pick])
+    np.testing.assert_array_equal(u[:-1], gu[pick])
+    with pytest.raises(pb.PicError):
+        ctx.get_particles_by_id(1, np.array([gi[0], gi[0]]))
