@@ -556,6 +556,9 @@ def main():
                     help="skip the unstaged reference kernel (keeps kernel profiles to the staged kernel)")
     ap.add_argument("--lb-steps", type=int, default=300)
     ap.add_argument("--lb-edges", action="store_true", help="also sweep the balancing study's box edge (16..128)")
+    ap.add_argument("--only", choices=["uneven", "lb"],
+                    help="run only the uneven-box comparison or only the balancing study and print its record "
+                         "(for per-workload kernel profiles; not the benchmark line)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -564,6 +567,12 @@ def main():
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.only == "uneven":
+        print(json.dumps({"uneven_boxes": uneven_boxes()}))
+        return
+    if args.only == "lb":
+        print(json.dumps({"lb_study": lb_study(steps=args.lb_steps)}))
+        return
     r = run_gpu(args)
     copy_gbs = copy_bandwidth()
     ms = r["ms_per_step"]
