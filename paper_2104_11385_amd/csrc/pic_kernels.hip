@@ -495,23 +495,98 @@ __global__ void k_box_counts(Particles<real> P, int np, Geom G, unsigned long lo
 }
 
 // Per-particle pass of the features: per-cell counts, per-box species counts,
-// outer-layer counts and the sum of |u|.
+// outer-layer counts and the sum of |u|.  As in k_box_counts, each wave walks
+// a run of kBoxRun particles and keeps wave-uniform running sums while all
+// its lanes see one box (the particles are grouped by tile), so that the
+// per-box atomics, which every wave of a box would otherwise take on the same
+// addresses, are taken about once per run.  The per-cell counts of the
+// block's particles are gathered in an LDS hash table (open addressing,
+// kFeatSlots slots, at most kFeatProbes probes, else a global atomic) and
+// added to the global counts once per distinct cell.
+constexpr int kFeatSlots = 2048;
+constexpr int kFeatProbes = 16;
+constexpr uint32_t kFeatEmpty = 0xFFFFFFFFu;
+static_assert(kFeatSlots == 1 << 11, "the slot hash takes the top 11 bits");
+
 template <typename real>
-__global__ void k_feat_particles(Particles<real> P, int np, Geom G, const int *box_hi, uint32_t *cellcount,
-                                 unsigned long long *spcnt, unsigned long long *edge, double *usum) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    int x, y, z;
-    unpack_cell(P.cell[p], x, y, z);
-    int b = box_of_cell(G, x, y, z);
-    atomicAdd(&cellcount[x + (size_t)G.n[0] * (y + (size_t)G.n[1] * z)], 1u);
-    int s = P.sp[p];
-    if (s < 2) wave_count_add(spcnt, 2 * b + s);
-    const int *lo = G.box_lo + 3 * b, *hi = box_hi + 3 * b;
-    bool on = x == lo[0] || x == hi[0] - 1 || y == lo[1] || y == hi[1] - 1 || z == lo[2] || z == hi[2] - 1;
-    if (on) wave_count_add(edge, b);
-    double ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
-    wave_sum_add(usum, b, sqrt(ux * ux + uy * uy + uz * uz));
+__global__ __launch_bounds__(256) void k_feat_particles(Particles<real> P, int np, Geom G, const int *box_hi,
+                                                        uint32_t *cellcount, unsigned long long *spcnt,
+                                                        unsigned long long *edge, double *usum) {
+    __shared__ uint32_t sKey[kFeatSlots], sCnt[kFeatSlots];
+    for (int i = threadIdx.x; i < kFeatSlots; i += blockDim.x) {
+        sKey[i] = kFeatEmpty;
+        sCnt[i] = 0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t p0 = w * kBoxRun;
+    const int p1 = (int)min((int64_t)np, p0 + kBoxRun);
+    int rb = -1;  // box of the running sums
+    unsigned long long r0 = 0, r1 = 0, re = 0;
+    double ru = 0.0;
+    auto flush = [&]() {
+        if (lane == 0 && rb >= 0) {
+            if (r0) atomicAdd(&spcnt[2 * rb], r0);
+            if (r1) atomicAdd(&spcnt[2 * rb + 1], r1);
+            if (re) atomicAdd(&edge[rb], re);
+            if (ru != 0.0) unsafeAtomicAdd(&usum[rb], ru);
+        }
+    };
+    for (int base = (int)p0; base < p1; base += 64) {
+        const int p = base + lane;
+        int b = -1, s = 0;
+        bool on = false;
+        double um = 0.0;
+        if (p < p1) {
+            int x, y, z;
+            unpack_cell(P.cell[p], x, y, z);
+            b = box_of_cell(G, x, y, z);
+            const uint32_t key = (uint32_t)x + (uint32_t)G.n[0] * ((uint32_t)y + (uint32_t)G.n[1] * (uint32_t)z);
+            uint32_t h = (key * 2654435761u) >> (32 - 11);
+            bool done = key == kFeatEmpty;  // the last cell of a domain of 2^32 cells goes to the global array
+            if (done) atomicAdd(&cellcount[key], 1u);
+            for (int q = 0; q < kFeatProbes && !done; ++q, h = (h + 1) & (kFeatSlots - 1)) {
+                uint32_t k = sKey[h];
+                if (k == kFeatEmpty) k = atomicCAS(&sKey[h], kFeatEmpty, key);
+                if (k == kFeatEmpty || k == key) {
+                    atomicAdd(&sCnt[h], 1u);
+                    done = true;
+                }
+            }
+            if (!done) atomicAdd(&cellcount[key], 1u);  // table full along the probe sequence
+            s = P.sp[p];
+            const int *lo = G.box_lo + 3 * b, *hi = box_hi + 3 * b;
+            on = x == lo[0] || x == hi[0] - 1 || y == lo[1] || y == hi[1] - 1 || z == lo[2] || z == hi[2] - 1;
+            const double ux = P.u[0][p], uy = P.u[1][p], uz = P.u[2][p];
+            um = sqrt(ux * ux + uy * uy + uz * uz);
+        }
+        const unsigned long long act = __ballot(b >= 0);
+        const int b0 = __shfl(b, 0);
+        if (__ballot(b == b0) == act) {
+            // the whole wave is in one box
+            if (b0 != rb) {
+                flush();
+                rb = b0;
+                r0 = r1 = re = 0;
+                ru = 0.0;
+            }
+            r0 += (unsigned long long)__popcll(__ballot(b >= 0 && s == 0));
+            r1 += (unsigned long long)__popcll(__ballot(b >= 0 && s == 1));
+            re += (unsigned long long)__popcll(__ballot(on));
+            double t = um;
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+            ru += t;
+        } else if (b >= 0) {
+            if (s < 2) wave_count_add(spcnt, 2 * b + s);
+            if (on) wave_count_add(edge, b);
+            wave_sum_add(usum, b, um);
+        }
+    }
+    flush();
+    __syncthreads();
+    for (int i = threadIdx.x; i < kFeatSlots; i += blockDim.x)
+        if (sCnt[i]) atomicAdd(&cellcount[sKey[i]], sCnt[i]);
 }
 
 __global__ void k_feat_boxes(const uint32_t *cellcount, Geom G, const int *box_hi, const unsigned long long *spcnt,
@@ -756,12 +831,14 @@ hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom
 hipError_t launch_features(int prec, const ParticlesRaw &P, int np, const Geom &G, int nb, const int *box_hi,
                            const FeatScratch &S, float *feat, hipStream_t st) {
     if (np > 0) {
+        const int64_t waves = ((int64_t)np + kBoxRun - 1) / kBoxRun;
+        const unsigned grid = (unsigned)((waves + 3) / 4);  // four waves per block
         if (prec == 8)
-            k_feat_particles<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(P), np, G, box_hi, S.cellcount, S.spcnt,
-                                                                    S.edge, S.usum);
+            k_feat_particles<double><<<grid, 256, 0, st>>>(cast<double>(P), np, G, box_hi, S.cellcount, S.spcnt,
+                                                           S.edge, S.usum);
         else
-            k_feat_particles<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(P), np, G, box_hi, S.cellcount, S.spcnt,
-                                                                   S.edge, S.usum);
+            k_feat_particles<float><<<grid, 256, 0, st>>>(cast<float>(P), np, G, box_hi, S.cellcount, S.spcnt, S.edge,
+                                                          S.usum);
     }
     k_feat_boxes<<<nb, 256, 0, st>>>(S.cellcount, G, box_hi, S.spcnt, S.edge, S.usum, feat);
     return hipGetLastError();

@@ -121,9 +121,13 @@ def test_learned_costs_fall_back_when_error_exceeds_15_percent():
     np.testing.assert_array_equal(c, h)
 
 
-def test_box_features_match_oracle():
-    wl = picsynth.small_workload(n=(32, 32, 32), box=16, order=2, ppc=3, seed=8,
-                                 species=("electrons", "protons"), precision=8, region_lo=(0, 0, 10),
+@pytest.mark.parametrize("precision,box,ppc", [(8, 16, 3), (4, 8, 12), (4, 16, 1)])
+def test_box_features_match_oracle(precision, box, ppc):
+    # (4, 8, 12): 64 boxes, waves that lie in one box and waves that straddle
+    # two; (4, 16, 1): more distinct cells per workgroup than its LDS table
+    # of cell counts holds, so that the global-atomic path is taken too
+    wl = picsynth.small_workload(n=(32, 32, 32), box=box, order=2, ppc=ppc, seed=8,
+                                 species=("electrons", "protons"), precision=precision, region_lo=(0, 0, 10),
                                  region_hi=(32, 32, 20), u_th=0.1)
     ctx = make_ctx(wl, load=True)
     ctx.step(4)
