@@ -265,7 +265,7 @@ def cubic_order(steps=40, warmup=5):
     return out
 
 
-def cpu_baseline(sample_particles=3_000_000):
+def cpu_baseline(sample_particles=8_000_000):
     """The FP64 oracle on the host: one step of a particle sample of the same
     workload (full grid, so the Yee update is included once), scaled to the
     full particle count: rate = N_p / (N_p * t_particle + t_yee)."""
