@@ -442,6 +442,8 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     sweep = S.sweep(rec["timer_step"], wl.boxes, ranks)
     sweep_s = time.perf_counter() - t0
     out = {"E_mean": summ, "c_max_over_c_avg": {st: {p: 1.0 / v for p, v in d.items()} for st, d in summ.items()},
+           "E_per_rebalance": {st: {p: [round(float(e), 4) for e in v] for p, v in d.items()} for st, d in E.items()
+                               if d},
            "balancing_step_cost": lb_cost, "loop_replay": loop, "halo_bytes_per_rebalance_mapping": comm,
            "interval_threshold_sweep": sweep, "sweep_seconds": sweep_s, "rebalances": int(len(rec["timer"]) - 1),
            "learned_over_timer": {p: summ["learned"][p] / summ["timer"][p] for p in summ["timer"]},
