@@ -236,7 +236,7 @@ def _div_e(F):
     return (F[0] - np.roll(F[0], 1, axis=2)) + (F[1] - np.roll(F[1], 1, axis=1)) + (F[2] - np.roll(F[2], 1, axis=0))
 
 
-@pytest.mark.parametrize("name", ["c2", "c4"])
+@pytest.mark.parametrize("name", ["c2", "c2-cubic", "c4"])
 def test_gauss_law_holds_over_25_steps_and_a_sort(name):
     # A property of the whole step at full size: with a charge-conserving
     # deposit on E's stagger, div E - rho keeps its initial value at every
@@ -246,12 +246,15 @@ def test_gauss_law_holds_over_25_steps_and_a_sort(name):
     # and the Yee passes at every node, not only sampled ones: the benchmark
     # workload (256^3, random initial fields) and the balancing-study
     # workload (384x384x768, 9.4e7 particles drifting at u_z = 0.05, so that
-    # ~2.5% of them change node each step), from its own initial state.
+    # ~2.5% of them change node each step), from its own initial state; and
+    # the benchmark workload with cubic shapes.
     import bench
     import oracle
     from paper_2104_11385_amd import picbal as pb
 
-    wl = bench.workload() if name == "c2" else picsynth.config(name)
+    wl = bench.workload() if name.startswith("c2") else picsynth.config(name)
+    if name == "c2-cubic":
+        wl.order = 3
     n = tuple(wl.n)
     q = np.array([s.charge for s in wl.species])
     print(f"full-size Gauss law: {name}, persistent + graph, 25 steps", flush=True)
@@ -268,10 +271,10 @@ def test_gauss_law_holds_over_25_steps_and_a_sort(name):
         rho = oracle.rho(wl.order, n, x, w, sp, q)
         return _div_e(ctx.get_fields()) - rho, rho
 
-    ctx = bench.make_ctx(wl) if name == "c2" else bench.ctx_for(wl)
+    ctx = bench.make_ctx(wl) if name.startswith("c2") else bench.ctx_for(wl)
     try:
         ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, True)
-        if name == "c2":
+        if name.startswith("c2"):
             ctx.set_fields(picsynth.random_fields(n, 7, amp=0.03))
         x, w, sp = particles(ctx)
         e = sp == 0
