@@ -310,3 +310,25 @@ def test_particles_by_id_match_full_copy():
     np.testing.assert_array_equal(u[:-1], gu[pick])
     with pytest.raises(pb.PicError):
         ctx.get_particles_by_id(1, np.array([gi[0], gi[0]]))
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+@pytest.mark.parametrize("axis", [0, 2])
+def test_packed_cell_limits(precision, axis):
+    # the largest domains the packed cell index holds along x (2048 cells,
+    # 11 bits) and z (1024, 10 bits): particles on the last cells cross the
+    # periodic face and back, under random fields, with quadratic shapes
+    n = [8, 8, 8]
+    n[axis] = 2048 if axis == 0 else 1024
+    lo = [0, 0, 0]
+    lo[axis] = n[axis] - 6
+    wl = picsynth.small_workload(n=tuple(n), box=8, order=2, ppc=2, seed=41, u_th=0.3,
+                                 species=("electrons", "protons"), precision=precision, region_lo=tuple(lo),
+                                 region_hi=tuple(n))
+    ctx = make_ctx(wl, load=False)
+    F = picsynth.random_fields(wl.n, 5, amp=0.02)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F)
+    ctx.step(10)
+    gx, _ = compare(ctx, wl, x, u, w, sp, ids, F, 10, TOL[precision])
+    # some particles wrapped through the face
+    assert (gx[:, axis] < 8).any() and (gx[:, axis] >= n[axis] - 8).any()
