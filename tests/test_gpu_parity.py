@@ -332,3 +332,42 @@ def test_packed_cell_limits(precision, axis):
     gx, _ = compare(ctx, wl, x, u, w, sp, ids, F, 10, TOL[precision])
     # some particles wrapped through the face
     assert (gx[:, axis] < 8).any() and (gx[:, axis] >= n[axis] - 8).any()
+
+
+@pytest.mark.parametrize("precision", [8, 4])
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_degenerate_offsets_and_velocities(precision, order):
+    # particles at rest, on cell faces (offset 0), on the half-cell points
+    # where the quadratic reference node changes (offset 1/2) and a rounding
+    # step below the next face (1 - 2^-40, which FP32 stores as the next
+    # cell's face), starting with no momentum, less than a rounding step of
+    # displacement, or enough to cross those points
+    wl = picsynth.small_workload(n=(16, 16, 16), box=8, order=order, ppc=1, seed=5,
+                                 species=("electrons", "protons"), precision=precision)
+    ctx = make_ctx(wl, load=False)
+    rng = np.random.default_rng(12)
+    offs = np.array([0.0, 0.5, 0.25, 1.0 - 2.0 ** -40])
+    speeds = np.array([0.0, 1e-17, -1e-17, 1e-6, -1e-6, 0.05, -0.05])
+    cells = rng.integers(0, 16, size=(len(offs) * len(speeds) * 3, 3))
+    x, u = [], []
+    k = 0
+    for o in offs:
+        for v in speeds:
+            for d in range(3):
+                pos = cells[k] + 0.5
+                pos[d] = cells[k][d] + o
+                vel = np.zeros(3)
+                vel[d] = v
+                x.append(pos); u.append(vel)
+                k += 1
+    x = np.array(x); u = np.array(u)
+    w = np.full(len(x), 0.05)
+    ids = np.arange(len(x))
+    ctx.set_particles(0, x, u, w, ids)
+    ctx.set_particles(1, np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0, np.int64))
+    # fields present, so that the gather at these points matters
+    F = picsynth.random_fields(wl.n, 9, amp=0.02)
+    ctx.set_fields(F)
+    ctx.step(4)
+    sp = np.zeros(len(x), np.int32)
+    compare(ctx, wl, x, u, w, sp, ids, F, 4, TOL[precision])
