@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # fp32 vector peak of the 256 CUs at 2.4 GHz: 4 SIMDs x 16 lanes x FMA (2 flops)
-# per CU and clock without packed-FP32 instructions (which this build does not
+# per CU and clock without packed-FP32 instructions (which this library does not
 # use), and with them
 FP32_VECTOR_PEAK_TFS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FP32_PACKED_PEAK_TFS = 2 * FP32_VECTOR_PEAK_TFS
@@ -566,7 +566,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: this library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.only == "uneven":

@@ -54,7 +54,7 @@ enum pic_status {
     PIC_ECFL = -4,         /* dt >= 1/sqrt(3): Yee scheme unstable in 3D          */
     PIC_ECAPACITY = -5,    /* more particles than the context was sized for       */
     PIC_ESTATE = -6,       /* call not valid in the current state                 */
-    PIC_EUNSUPPORTED = -7  /* valid request this build does not implement         */
+    PIC_EUNSUPPORTED = -7  /* valid request this library does not implement       */
 };
 
 enum { PIC_FP32 = 4, PIC_FP64 = 8 };
