@@ -1,6 +1,6 @@
 """GPU parity: the HIP path against the FP64 oracle on identical seeded inputs.
 
-Tolerances (written here, derived in the design doc):
+Tolerances (derived from the arithmetic of each precision):
   FP64 library vs FP64 oracle: 1e-12, relative to the largest value of each
   quantity (positions per particle relative to max(1, |x|)).
   FP32 library vs FP64 oracle after 10 steps: 1e-5 the same way.
