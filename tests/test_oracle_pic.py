@@ -325,3 +325,44 @@ def test_pic_step_wrap_rule():
     x = np.array([[0.0, 2.5, 2.5]]); u = np.array([[-1e-18, 0.0, 0.0]])
     oracle.pic_step(1, n, 0.5, x, u, np.zeros(1), np.zeros(1, np.int32), [-1.0], [1.0], F, 1)
     assert x[0, 0] == 0.0
+
+
+# --------------------------------------------------------------------------
+# Charge density (used as the reference in the Gauss-law checks)
+# --------------------------------------------------------------------------
+
+# 1D B-spline values at the nodes around a particle sitting exactly on node 0
+_ON_NODE = {1: {0: 1.0}, 2: {-1: 0.125, 0: 0.75, 1: 0.125}, 3: {-1: 1 / 6, 0: 2 / 3, 1: 1 / 6}}
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_rho_of_a_particle_on_a_node(m):
+    # the tensor product of the 1D node values, at the particle's node and
+    # its neighbours, periodic through the domain's faces
+    n = np.array([6, 6, 6])
+    for node in ([2, 3, 4], [0, 5, 0]):
+        x = np.array([node], dtype=float)
+        r = oracle.rho(m, n, x, np.array([0.5]), np.array([0], np.int32), [-2.0])
+        want = np.zeros((6, 6, 6))
+        for dx, vx in _ON_NODE[m].items():
+            for dy, vy in _ON_NODE[m].items():
+                for dz, vz in _ON_NODE[m].items():
+                    want[(node[2] + dz) % 6, (node[1] + dy) % 6, (node[0] + dx) % 6] += -1.0 * vx * vy * vz
+        np.testing.assert_allclose(r, want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_rho_total_charge_and_translation(m):
+    # partition of unity: the nodes hold every particle's charge q w; moving
+    # all particles by whole cells moves rho by the same cells
+    rng = np.random.default_rng(7)
+    n = np.array([8, 6, 10])
+    x = rng.random((50, 3)) * n
+    w = rng.random(50)
+    sp = rng.integers(0, 2, 50).astype(np.int32)
+    q = [-1.0, 3.0]
+    r = oracle.rho(m, n, x, w, sp, q)
+    assert abs(r.sum() - np.sum(np.array(q)[sp] * w)) < 1e-12
+    shift = np.array([3, 1, 7])
+    r2 = oracle.rho(m, n, (x + shift) % n, w, sp, q)
+    np.testing.assert_allclose(r2, np.roll(r, (7, 1, 3), axis=(0, 1, 2)), rtol=0, atol=1e-13)
