@@ -311,9 +311,10 @@ __global__ void k_fill(T *a, T v, size_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Yee update in streaming passes.  Threads own (x, y) columns and march
-// along z, carrying the z neighbours in registers; x and y neighbours are
-// read through the caches.  X is a half-step B buffer.
+// Yee update in streaming passes.  Each thread owns an (x, y) column over
+// YSZ z-planes (one plane with the current blocks), carrying the z
+// neighbour in registers along the march; x and y neighbours are read
+// through the caches.  X is a half-step B buffer.
 //   half:  X = B^{n+1/2} = B^n - dt/2 curl E^n (only when X is not current)
 //   E:     E^{n+1} = E^n + dt (curl X - J) into the other E buffer, and the
 //          next step's J buffer cleared; z-planes that the deposit left
