@@ -316,10 +316,12 @@ def ctx_for(wl, stream=None):
     return pb.pic_init(wl.n, wl.boxes, sp, wl.dt, wl.order, prec, wl.seed, b_ext=wl.b_ext, stream=stream)
 
 
-def uneven_boxes(steps=5, warmup=2):
+def uneven_boxes(steps=20, warmup=2):
     """512^3 cells in 4096 mixed boxes (256 of 64^3, 1792 of 32^3, 2048 of
     16^3) with per-box ppc = min(64, round(LogNormal(1.5, 1.2))): 1.13e9
-    electrons.  Persistent queue (graph-replayed) against one launch per box."""
+    electrons.  Persistent queue (graph-replayed) against one launch per box.
+    Each mode times 20 steps, so that its time includes one particle sort
+    (every 20 steps by default) as a long run's does."""
     import picsynth
     from paper_2104_11385_amd import picbal as pb
     wl = picsynth.config("c3")

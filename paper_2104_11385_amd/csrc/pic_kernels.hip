@@ -251,15 +251,46 @@ __device__ __forceinline__ int sub_queue(const int *segstart, int t, int ntiles,
     return x < kSubQueues ? x : kSubQueues - 1;
 }
 
+// Reserves cnt consecutive slots of counter arr[key] for every lane with
+// want set, with one atomic per distinct key in the wave (adjacent tiles
+// mostly share a sub-queue and size class, so per-lane atomics would queue
+// on a few addresses).  Every lane of the wave calls it.  Returns the lane's
+// first slot (0 for lanes without want).
+__device__ inline int wave_reserve(int *arr, int key, int cnt, bool want) {
+    const int lane = (int)__lane_id();
+    unsigned long long todo = __ballot(want);
+    int pos = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lkey = __shfl(key, leader);
+        const bool mine = want && key == lkey;
+        const int c = mine ? cnt : 0;
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        const int total = __shfl(incl, 63);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&arr[lkey], total);
+        base = __shfl(base, leader);
+        if (mine) pos = base + incl - c;
+        todo &= ~__ballot(mine);
+    }
+    return pos;
+}
+
 __global__ void k_queue_count(const int *segstart, int ntiles, int nsp, int chunk, int ncls, int *cls_cnt) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
-    int n = segstart[(t + 1) * nsp] - segstart[t * nsp];
-    if (n == 0) return;
-    int x = sub_queue(segstart, t, ntiles, nsp);
-    int full = n / chunk, rem = n - full * chunk;
-    if (full) atomicAdd(&cls_cnt[x * ncls], full);
-    if (rem) atomicAdd(&cls_cnt[x * ncls + size_class(rem, chunk, ncls)], 1);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = 0, x = 0;
+    if (t < ntiles) {
+        n = segstart[(t + 1) * nsp] - segstart[t * nsp];
+        if (n > 0) x = sub_queue(segstart, t, ntiles, nsp);
+    }
+    const int full = n / chunk, rem = n - full * chunk;
+    (void)wave_reserve(cls_cnt, x * ncls, full, full > 0);
+    (void)wave_reserve(cls_cnt, x * ncls + (rem ? size_class(rem, chunk, ncls) : 0), 1, rem > 0);
 }
 
 // Bucket offsets: sub-queue major, size class (largest first) minor.  One
@@ -279,20 +310,18 @@ __global__ void k_queue_scan(int *cls_cnt, int *cursor, int ncls, int *qbounds) 
 
 __global__ void k_queue_fill(const int *segstart, int ntiles, int nsp, int chunk, int ncls, int *cursor,
                              int4 *queue) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
-    int b = segstart[t * nsp], n = segstart[(t + 1) * nsp] - b;
-    if (n == 0) return;
-    int x = sub_queue(segstart, t, ntiles, nsp);
-    int full = n / chunk, rem = n - full * chunk;
-    if (full) {
-        int pos = atomicAdd(&cursor[x * ncls], full);
-        for (int j = 0; j < full; ++j) queue[pos + j] = make_int4(t, b + j * chunk, b + (j + 1) * chunk, 0);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = 0, n = 0, x = 0;
+    if (t < ntiles) {
+        b = segstart[t * nsp];
+        n = segstart[(t + 1) * nsp] - b;
+        if (n > 0) x = sub_queue(segstart, t, ntiles, nsp);
     }
-    if (rem) {
-        int pos = atomicAdd(&cursor[x * ncls + size_class(rem, chunk, ncls)], 1);
-        queue[pos] = make_int4(t, b + full * chunk, b + n, 0);
-    }
+    const int full = n / chunk, rem = n - full * chunk;
+    const int pf = wave_reserve(cursor, x * ncls, full, full > 0);
+    for (int j = 0; j < full; ++j) queue[pf + j] = make_int4(t, b + j * chunk, b + (j + 1) * chunk, 0);
+    const int pr = wave_reserve(cursor, x * ncls + (rem ? size_class(rem, chunk, ncls) : 0), 1, rem > 0);
+    if (rem) queue[pr] = make_int4(t, b + full * chunk, b + n, 0);
 }
 
 __global__ void k_reset_heads(int *heads) {
