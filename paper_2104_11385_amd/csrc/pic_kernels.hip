@@ -232,6 +232,35 @@ __global__ void k_sort_scatter(Particles<real> S, Particles<real> D, int np, con
     D.sp[d] = S.sp[p];
 }
 
+// Node-major order as a gather: the destination of each particle is written
+// to perm (one 4-byte scattered store per particle), then every destination
+// slot reads its particle, so that the particle data are written in full
+// contiguous lines.
+__global__ void k_sort_perm(int np, const uint32_t *key, const uint32_t *rank, const uint32_t *cellstart,
+                            const int *segstart, int Tvol, uint32_t *perm) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const uint32_t k = key[p];
+    const int ts = (int)(k / (uint32_t)Tvol);
+    perm[segstart[ts] + (int)cellstart[k] + (int)rank[p]] = (uint32_t)p;
+}
+
+template <typename real>
+__global__ void k_sort_gather(Particles<real> S, Particles<real> D, int np, const uint32_t *perm) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= np) return;
+    const int p = (int)perm[d];
+    D.cell[d] = S.cell[p];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        D.f[c][d] = S.f[c][p];
+        D.u[c][d] = S.u[c][p];
+    }
+    D.w[d] = S.w[p];
+    D.id[d] = S.id[p];
+    D.sp[d] = S.sp[p];
+}
+
 // ---------------------------------------------------------------------------
 // Work queue for the persistent kernel: tiles cut into chunks of at most
 // `chunk` particles, ordered largest first (size classes).
@@ -716,7 +745,12 @@ hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, i
         k_sort_levels<<<nts, G.Tvol, 0, st>>>(W.cellcnt, W.cellstart, W.segstart, W.table, G.Tvol);
         table = W.table;
     }
-    if (np > 0) {
+    if (np > 0 && node_major) {
+        // W.table (capacity entries) serves as the permutation
+        k_sort_perm<<<nblk(np, 256), 256, 0, st>>>(np, W.key, W.rank, W.cellstart, W.segstart, G.Tvol, W.table);
+        if (prec == 8) k_sort_gather<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(S), cast<double>(D), np, W.table);
+        else k_sort_gather<float><<<nblk(np, 256), 256, 0, st>>>(cast<float>(S), cast<float>(D), np, W.table);
+    } else if (np > 0) {
         if (prec == 8)
             k_sort_scatter<double><<<nblk(np, 256), 256, 0, st>>>(cast<double>(S), cast<double>(D), np, W.key, W.rank,
                                                                    W.cellstart, W.segstart, table, G.Tvol);
