@@ -211,6 +211,8 @@ __global__ void k_sort_levels(const uint32_t *cellcnt, const uint32_t *cellstart
     }
 }
 
+// Moves each particle to its slot (the interleaved order, whose level table
+// maps the counting-sort position to the slot).
 template <typename real>
 __global__ void k_sort_scatter(Particles<real> S, Particles<real> D, int np, const uint32_t *key,
                                const uint32_t *rank, const uint32_t *cellstart, const int *segstart,
