@@ -184,7 +184,9 @@ PIC_API int pic_autotune(pic_ctx *ctx, int32_t steps, pic_tuning *best, double *
  * timer cycles from the current box features; it falls back to HEURISTIC
  * when no model is loaded, or when the prediction made at the previous
  * LEARNED call missed the most recent DEVICE_TIMER reading by more than 15%
- * relative error, sum |pred - t| / sum t over boxes; that reading should
+ * relative error, sum |s pred - t| / sum t over boxes with s = sum t /
+ * sum pred (a common factor does not count: mappings and E depend only on
+ * cost ratios); that reading should
  * cover the whole interval the prediction was made for (read the counters
  * at its end, without a reset inside it).  Intended order per balancing
  * step: read DEVICE_TIMER, reset, then LEARNED.  *used_strategy (nullable) reports which strategy produced
@@ -281,18 +283,27 @@ PIC_API int32_t pic_mlp_nparam(void);
 /* Trains the 16-64-64-1 ReLU network (bf16 matrix-core operands, fp32
  * accumulation and master weights) on the device to predict y from X
  * (X[n][16] raw features, standardised internally with their mean and std;
- * y[n] = ln(1 + device-timer cycles), so that boxes without work are
- * represented; PIC_COST_LEARNED then reports max(0, exp(yhat) - 1)),
- * minimising the mean squared error with Adam
+ * a feature that is constant over the training set gets std 0 and enters
+ * as 0 whatever its value; y[n] = ln(1 + device-timer cycles), so that
+ * boxes without work are represented).  The network models the residual
+ * r = y - ln(1 + N), N = the box's particles from features 0 and 1 (the
+ * log of the cycles per particle), standardised: it is fitted to
+ * (r - mean_r) / std_r, and yhat = ln(1 + N) + mean_r + std_r * output.
+ * PIC_COST_LEARNED reports max(0, exp(yhat) - 1) with the predicted
+ * residual clamped to [min r, max r] of the training set.  Minimises the
+ * mean squared error with Adam
  * (lr 1e-3, betas 0.9/0.999, eps 1e-8), minibatch `batch`, `epochs` passes.
  * perm[epochs][n] (nullable) gives each epoch's sample order; NULL uses a
  * seeded shuffle.  init_w[nparam] (nullable) sets the initial weights, else
- * Kaiming-uniform from seed.  loss_per_epoch[epochs] (nullable) out. */
+ * Kaiming-uniform from seed.  loss_per_epoch[epochs] (nullable) out, the
+ * mean squared error in units of y. */
 PIC_API int pic_mlp_train(pic_ctx *ctx, const float *X, const float *y, int64_t n, int32_t epochs,
                           int32_t batch, const int32_t *perm, const float *init_w, uint64_t seed,
                           float *loss_per_epoch);
 
-/* Predicts yhat[n] = network(standardise(X)) on the device. */
+/* Predicts yhat[n] = ln(1 + N) + mean_r + std_r * network(standardise(X))
+ * on the device (no clamp; a model set from nparam or nparam + 32 floats
+ * predicts network(standardise(X))). */
 PIC_API int pic_mlp_predict(pic_ctx *ctx, const float *X, int64_t n, float *yhat);
 
 /* One forward + backward pass on a batch without updating weights:
@@ -303,7 +314,14 @@ PIC_API int pic_mlp_loss_grad(pic_ctx *ctx, const float *X, const float *y, int6
                               float *loss, float *grad);
 
 /* Weights in the layout W1[64][16] b1[64] W2[64][64] b2[64] W3[64] b3[1],
- * followed by the 16 feature means and 16 feature stds (nparam + 32 floats). */
+ * followed by the 16 feature means and 16 feature stds (0: feature ignored)
+ * and then mean_r, std_r, min r, max r and the residual flag (1: the
+ * network models y - ln(1 + N); 0: y itself): nparam, nparam + 32 or
+ * nparam + 37 floats.  pic_mlp_set_weights with nparam floats keeps the
+ * feature standardisation; with fewer than nparam + 37 it sets mean_r = 0,
+ * std_r = 1, no clamp (min r > max r also means no clamp) and flag 0;
+ * std_r <= 0 -> PIC_EINVAL.  pic_mlp_get_weights needs n >= nparam + 32 and
+ * writes the target transform when n >= nparam + 37. */
 PIC_API int pic_mlp_set_weights(pic_ctx *ctx, const float *w, int64_t n);
 PIC_API int pic_mlp_get_weights(pic_ctx *ctx, float *w, int64_t n);
 

@@ -37,9 +37,11 @@ struct Particles {
     uint8_t *sp;
 };
 
-// Tile origin (global cell coordinates of its lowest corner) and owning box.
+// Tile origin (global cell coordinates of its lowest corner), owning box,
+// and that box's lowest and highest cell, packed like a particle's cell.
 struct TileDesc {
     int x0, y0, z0, box;
+    uint32_t box_lo, box_hi;
 };
 
 // Geometry needed to map a cell to (box, tile, cell-in-tile).
@@ -59,6 +61,14 @@ struct Geom {
 
 enum { MODE_PER_BOX = 0, MODE_BATCHED = 1, MODE_PERSISTENT = 2 };
 
+// Box bounds and the cell -> box lookup, in device memory (read by the
+// gather-push-deposit kernel only for particles outside their tile's box).
+struct BoxMap {
+    const int *boxes6;       // [nb][6] lo, hi of each box
+    const int *coarse_box;   // box of each coarse cell (cell / g)
+    int g[3], cg[3];         // coarse cell edge and coarse grid size
+};
+
 // Arguments of the gather-push-deposit kernel.
 template <typename real>
 struct GpdArgs {
@@ -75,6 +85,7 @@ struct GpdArgs {
     real coefq[kMaxSpecies];   // -q / dt
     unsigned long long *cycles;    // [nb]
     unsigned long long *rtc;       // [nb]
+    const BoxMap *bmap;            // box bounds and the cell -> box map
     unsigned int *slow;            // particles that took the global path
     int *jdirty;                   // [n[2]] set to 1 for every z-plane of J written
     int mode;

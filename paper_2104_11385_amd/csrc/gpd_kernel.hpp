@@ -719,6 +719,30 @@ __device__ __forceinline__ void deposit_runs(const Deferred<real> &df, double *s
     runs_comp<real, M, 2>(J, DW, coef, rr, keep);
 }
 
+// Slots of a block's table of foreign boxes: a tile and the cells its
+// particles may drift into before the next sort meet at most 8 boxes of the
+// smallest edge (16 cells) that tiles nest in.
+constexpr int kForeignSlots = 16;
+
+// Counts one particle whose cell lies outside its tile's box under the box
+// that holds the cell (open addressing; a full table leaves the particle
+// with the tile's box).
+__device__ __forceinline__ void note_foreign(const BoxMap &bm, uint32_t cell, int *sbox, unsigned *scnt,
+                                             unsigned &sany) {
+    int x, y, z;
+    unpack_cell(cell, x, y, z);
+    const int b = bm.coarse_box[(x / bm.g[0]) + bm.cg[0] * ((y / bm.g[1]) + bm.cg[1] * (z / bm.g[2]))];
+    for (int k = 0; k < kForeignSlots; ++k) {
+        const int slot = (b + k) & (kForeignSlots - 1);
+        const int prev = atomicCAS(&sbox[slot], -1, b);
+        if (prev == -1 || prev == b) {
+            atomicAdd(&scnt[slot], 1u);
+            sany = 1;
+            return;
+        }
+    }
+}
+
 template <typename real, int M, int TX, int TY, int TZ, int H, bool R>
 __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
@@ -731,6 +755,11 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     __shared__ unsigned int sSlow;
     __shared__ int sItem[3];
     __shared__ int sQn[8];  // queue lengths of the block's waves at the end of an item
+    // particles of the item whose cell lies outside the tile's box (they
+    // drifted across a box face since the last sort), counted per box
+    __shared__ int sFBox[kForeignSlots];
+    __shared__ unsigned sFCnt[kForeignSlots];
+    __shared__ unsigned sFAny;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nsp = A.nsp;
     const int home = blockIdx.x % kSubQueues;  // blocks are dealt round-robin over the XCDs
@@ -743,6 +772,11 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = 0.0;
     for (int iter = 0;; ++iter) {
         int tile, pbeg, pend;
+        if (tid < kForeignSlots) {
+            sFBox[tid] = -1;
+            sFCnt[tid] = 0;
+        }
+        if (tid == 0) sFAny = 0;
         if (A.mode == MODE_PERSISTENT) {
             // own XCD's sub-queue first, then steal from the others
             if (tid == 0) {
@@ -762,9 +796,10 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 }
             }
             __syncthreads();
-            tile = sItem[0];
-            pbeg = sItem[1];
-            pend = sItem[2];
+            // the same for every thread: held in scalar registers
+            tile = __builtin_amdgcn_readfirstlane(sItem[0]);
+            pbeg = __builtin_amdgcn_readfirstlane(sItem[1]);
+            pend = __builtin_amdgcn_readfirstlane(sItem[2]);
             if (tile < 0) break;
         } else {
             if (iter > 0) break;
@@ -777,8 +812,13 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 pend = A.segstart[(tile + 1) * nsp];
             }
             if (pbeg >= pend) break;
+            __syncthreads();  // the table of foreign boxes is clear
         }
         const TileDesc td = A.tiles[tile];
+        // the tile's box, for charging each particle's work to the box that
+        // holds its cell at the start of the step (wave-uniform)
+        const uint32_t box_lo = __builtin_amdgcn_readfirstlane(td.box_lo);
+        const uint32_t box_hi = __builtin_amdgcn_readfirstlane(td.box_hi);
 
         // stage E and B of the tile window (one index computation serves the
         // six components; windows inside the domain need no wrap)
@@ -862,6 +902,24 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 df.want = false;
                 df.keep = false;
                 df.rel = 0x080808;  // the tile origin, for lanes without a particle
+                if (timed) {
+                    // particles that drifted out of the tile's box since the
+                    // last sort are counted under the box that holds them
+                    // (the packed bounds are unpacked here, in scalar
+                    // registers, rather than kept unpacked across the loop)
+                    uint32_t bl = box_lo, bh = box_hi;
+                    asm volatile("" : "+s"(bl), "+s"(bh));
+                    int cx, cy, cz, lx, ly, lz, hx, hy, hz;
+                    unpack_cell(cur.cell, cx, cy, cz);
+                    unpack_cell(bl, lx, ly, lz);
+                    unpack_cell(bh, hx, hy, hz);
+                    // branch-free: one ballot, and a branch only for a wave
+                    // that holds such a particle
+                    const bool foreign = (p < se) & (((unsigned)(cx - lx) > (unsigned)(hx - lx)) |
+                                                     ((unsigned)(cy - ly) > (unsigned)(hy - ly)) |
+                                                     ((unsigned)(cz - lz) > (unsigned)(hz - lz)));
+                    if (__ballot(foreign) && foreign) note_foreign(*A.bmap, cur.cell, sFBox, sFCnt, sFAny);
+                }
                 PState<real> moved;
                 if (p < se)
                     push_particle<real, M, TX, TY, TZ, H, R>(A, p, cur, td, hq, cq, sEB, sJ, nslow, df, moved);
@@ -958,8 +1016,32 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
         }
         if (tid == 0) {
             if (timed) {
-                atomicAdd(&A.cycles[td.box], sCyc);
-                atomicAdd(&A.rtc[td.box], sRtc);
+                // the item's cycles are split over the boxes that hold its
+                // particles, in proportion to their counts (particles that
+                // found no free slot stay with the tile's box)
+                const unsigned long long cyc = sCyc, rtc = sRtc;
+                unsigned long long cf = 0, rf = 0;
+                unsigned nf = 0;
+                const unsigned n_item = (unsigned)(pend - pbeg);
+                if (sFAny) {
+                    const double inv = 1.0 / (double)n_item;
+                    for (int k = 0; k < kForeignSlots; ++k) {
+                        const int b = sFBox[k];
+                        if (b < 0) continue;
+                        const unsigned cnt = sFCnt[k];
+                        const unsigned long long c = (unsigned long long)((double)cyc * (double)cnt * inv);
+                        const unsigned long long r = (unsigned long long)((double)rtc * (double)cnt * inv);
+                        if (c) atomicAdd(&A.cycles[b], c);
+                        if (r) atomicAdd(&A.rtc[b], r);
+                        cf += c;
+                        rf += r;
+                        nf += cnt;
+                    }
+                }
+                if (nf < n_item) {
+                    atomicAdd(&A.cycles[td.box], cyc - cf);
+                    atomicAdd(&A.rtc[td.box], rtc - rf);
+                }
             }
             if (sSlow) atomicAdd(A.slow, sSlow);
         }
@@ -1014,6 +1096,7 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
     }
     A.cycles = L.cycles;
     A.rtc = L.rtc;
+    A.bmap = L.bmap;
     A.slow = L.slow;
     A.jdirty = L.jdirty;
     A.mode = L.mode;

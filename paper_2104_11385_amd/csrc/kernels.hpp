@@ -75,6 +75,7 @@ struct GpdLaunch {
     double h[kMaxSpecies];
     double coefq[kMaxSpecies];
     unsigned long long *cycles, *rtc;
+    const BoxMap *bmap;        // device copy of the box bounds and map
     unsigned int *slow;
     int *jdirty;               // [nz] z-planes of J the deposit touched
     int mode;

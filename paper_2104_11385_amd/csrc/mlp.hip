@@ -27,7 +27,13 @@ struct MlpState {
     float *X = nullptr, *y = nullptr, *yhat = nullptr;
     int *perm = nullptr;
     int64_t cap = 0;
-    float h_mean[NI], h_std[NI];
+    float h_mean[NI], h_std[NI];  // std 0: a feature constant in training, ignored
+    // target transform: with base = 1 the network models the residual
+    // r = y - ln(1 + N) (N = the box's particles, from features 0 and 1),
+    // else r = y; it is trained on (r - ymean) / ystd and predicts
+    // r = ymean + ystd * output; [ymin, ymax] is the training residuals'
+    // range, to which learned costs clamp r (ymin > ymax: no clamp)
+    float ymean = 0.f, ystd = 1.f, ymin = 1.f, ymax = 0.f, base = 0.f;
     bool ready = false;
     int64_t t = 0;
 };
@@ -326,10 +332,17 @@ static int mlp_ensure(pic_ctx *ctx, int64_t n) {
 static int mlp_upload_norm(pic_ctx *ctx) {
     MlpState &M = *ctx->mlp;
     float istd[NI];
-    for (int i = 0; i < NI; ++i) istd[i] = 1.f / M.h_std[i];
+    for (int i = 0; i < NI; ++i) istd[i] = M.h_std[i] > 0.f ? 1.f / M.h_std[i] : 0.f;
     MLPC(hipMemcpyAsync(M.mean, M.h_mean, 4 * NI, hipMemcpyHostToDevice, ctx->st));
     MLPC(hipMemcpyAsync(M.istd, istd, 4 * NI, hipMemcpyHostToDevice, ctx->st));
     return PIC_OK;
+}
+
+// ln(1 + N) of a box from its raw features 0 and 1 (ln(1 + N_s) of the
+// first two species).
+static double ln1p_particles(const float *x) {
+    double ne = std::max(0.0, std::expm1((double)x[0])), ni = std::max(0.0, std::expm1((double)x[1]));
+    return std::log1p(ne + ni);
 }
 
 static int mlp_forward(pic_ctx *ctx, const float *dX, int64_t n, float *dyhat) {
@@ -350,19 +363,29 @@ static int mlp_forward(pic_ctx *ctx, const float *dX, int64_t n, float *dyhat) {
 // ln(1 + cycles) so that boxes without work are represented); falls back to
 // the heuristic when no model is loaded, or when the prediction made for the
 // interval just measured missed the measured timer costs by more than 15%
-// relative error, sum_b |pred_b - t_b| / sum_b t_b (errors weighted by cost,
-// so a box holding a few stray particles cannot trigger the fallback alone).
+// relative error, sum_b |pred_b s - t_b| / sum_b t_b with the prediction
+// scaled to the measured total, s = sum t / sum pred.  Errors are weighted
+// by cost, so that a box holding a few stray particles cannot trigger the
+// fallback alone, and a common factor (a clock rate that differs from the
+// training runs') does not count: mappings and E depend only on cost ratios.
 int pic_ctx::learned_costs(double *costs, int *used) {
     *used = PIC_COST_HEURISTIC;
     if (!mlp || !mlp->ready) return PIC_OK;
     bool fallback = false;
     if (last_pred.size() == (size_t)nb && last_timer.size() == (size_t)nb) {
-        double err = 0.0, tot = 0.0;
+        double ps = 0.0, tot = 0.0;
         for (int b = 0; b < nb; ++b) {
-            err += std::fabs(last_pred[b] - last_timer[b]);
+            ps += last_pred[b];
             tot += last_timer[b];
         }
-        mare = tot > 0.0 ? err / tot : 0.0;
+        if (tot > 0.0 && ps > 0.0) {
+            const double sc = tot / ps;
+            double err = 0.0;
+            for (int b = 0; b < nb; ++b) err += std::fabs(last_pred[b] * sc - last_timer[b]);
+            mare = err / tot;
+        } else {
+            mare = (tot > 0.0) != (ps > 0.0) ? 1.0 : 0.0;
+        }
         fallback = mare > 0.15;
     }
     int rc = features_device();
@@ -370,12 +393,21 @@ int pic_ctx::learned_costs(double *costs, int *used) {
     if ((rc = mlp_ensure(this, nb))) return rc;
     if ((rc = mlp_upload_norm(this))) return rc;
     if ((rc = mlp_forward(this, d_feat, nb, mlp->yhat))) return rc;
-    std::vector<float> yh(nb);
+    std::vector<float> yh(nb), feat((size_t)nb * NI);
     hipError_t e = hipMemcpyAsync(yh.data(), mlp->yhat, 4 * (size_t)nb, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(feat.data(), d_feat, 4 * (size_t)nb * NI, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "learned costs");
     last_pred.resize(nb);
-    for (int b = 0; b < nb; ++b) last_pred[b] = std::max(0.0, std::expm1((double)yh[b]));
+    const MlpState &M = *mlp;
+    for (int b = 0; b < nb; ++b) {
+        // back to ln(1 + cycles), the residual clamped to the range the model
+        // was trained on
+        double r = (double)M.ymean + (double)M.ystd * (double)yh[b];
+        if (M.ymin <= M.ymax) r = std::min(std::max(r, (double)M.ymin), (double)M.ymax);
+        const double y = r + (M.base != 0.f ? ln1p_particles(&feat[(size_t)b * NI]) : 0.0);
+        last_pred[b] = std::max(0.0, std::expm1(y));
+    }
     if (fallback) return PIC_OK;
     for (int b = 0; b < nb; ++b) costs[b] = last_pred[b];
     *used = PIC_COST_LEARNED;
@@ -400,7 +432,9 @@ PIC_API int pic_mlp_train(pic_ctx *ctx, const float *X, const float *y, int64_t 
     int rc;
     if ((rc = mlp_ensure(ctx, n))) return rc;
     MlpState &M = *ctx->mlp;
-    // standardisation from the training set (constant features keep std 1)
+    // standardisation from the training set; a feature that is constant in
+    // it gets std 0 (standardised input 0 whatever its value, so that a
+    // weight it never trained cannot act on new data)
     for (int i = 0; i < NI; ++i) {
         double s = 0.0, s2 = 0.0;
         for (int64_t r = 0; r < n; ++r) s += X[r * NI + i];
@@ -411,7 +445,32 @@ PIC_API int pic_mlp_train(pic_ctx *ctx, const float *X, const float *y, int64_t 
         }
         double sd = std::sqrt(s2 / (double)n);
         M.h_mean[i] = (float)mu;
-        M.h_std[i] = sd > 1e-6 ? (float)sd : 1.f;
+        M.h_std[i] = sd > 1e-6 ? (float)sd : 0.f;
+    }
+    // The network models the residual r = y - ln(1 + N): the log of a box's
+    // cycles per particle, whose spread is far narrower than that of the
+    // cycles themselves (the heaviest boxes, which decide the balance, are
+    // then fitted as well as the light ones).  The residuals are
+    // standardised, so that the bf16 layers produce an output of order one.
+    std::vector<float> ys(n);
+    {
+        std::vector<double> res(n);
+        for (int64_t r = 0; r < n; ++r) res[r] = (double)y[r] - ln1p_particles(X + r * NI);
+        double s = 0.0, s2 = 0.0, lo = res[0], hi = res[0];
+        for (int64_t r = 0; r < n; ++r) {
+            s += res[r];
+            lo = std::min(lo, res[r]);
+            hi = std::max(hi, res[r]);
+        }
+        double mu = s / (double)n;
+        for (int64_t r = 0; r < n; ++r) s2 += (res[r] - mu) * (res[r] - mu);
+        double sd = std::sqrt(s2 / (double)n);
+        M.ymean = (float)mu;
+        M.ystd = sd > 1e-6 ? (float)sd : 1.f;
+        M.ymin = (float)lo;
+        M.ymax = (float)hi;
+        M.base = 1.f;
+        for (int64_t r = 0; r < n; ++r) ys[r] = (float)((res[r] - mu) / (double)M.ystd);
     }
     if ((rc = mlp_upload_norm(ctx))) return rc;
     // initial weights: given, or Kaiming-uniform (biases zero)
@@ -433,7 +492,7 @@ PIC_API int pic_mlp_train(pic_ctx *ctx, const float *X, const float *y, int64_t 
     k_zero<<<(NPARAM + 255) / 256, 256, 0, ctx->st>>>(M.v, NPARAM);
     k_zero<<<(NPARAM + 255) / 256, 256, 0, ctx->st>>>(M.g, NPARAM);
     MLPC(hipMemcpyAsync(M.X, X, 4 * NI * (size_t)n, hipMemcpyHostToDevice, ctx->st));
-    MLPC(hipMemcpyAsync(M.y, y, 4 * (size_t)n, hipMemcpyHostToDevice, ctx->st));
+    MLPC(hipMemcpyAsync(M.y, ys.data(), 4 * (size_t)n, hipMemcpyHostToDevice, ctx->st));
     M.t = 0;
     const float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     std::vector<int32_t> order(n);
@@ -472,7 +531,7 @@ PIC_API int pic_mlp_train(pic_ctx *ctx, const float *X, const float *y, int64_t 
             float l = 0.f;
             MLPC(hipMemcpyAsync(&l, M.loss, 4, hipMemcpyDeviceToHost, ctx->st));
             MLPC(hipStreamSynchronize(ctx->st));
-            loss_per_epoch[ep] = l / (float)n;
+            loss_per_epoch[ep] = l / (float)n * M.ystd * M.ystd;  // in units of y (= of r)
         }
     }
     MLPC(hipStreamSynchronize(ctx->st));
@@ -494,6 +553,10 @@ PIC_API int pic_mlp_predict(pic_ctx *ctx, const float *X, int64_t n, float *yhat
     if ((rc = mlp_forward(ctx, M.X, n, M.yhat))) return rc;
     MLPC(hipMemcpyAsync(yhat, M.yhat, 4 * (size_t)n, hipMemcpyDeviceToHost, ctx->st));
     MLPC(hipStreamSynchronize(ctx->st));
+    if (M.ymean != 0.f || M.ystd != 1.f || M.base != 0.f)
+        for (int64_t r = 0; r < n; ++r)
+            yhat[r] = (float)((double)M.ymean + (double)M.ystd * (double)yhat[r] +
+                              (M.base != 0.f ? ln1p_particles(X + r * NI) : 0.0));
     return PIC_OK;
 }
 
@@ -541,15 +604,30 @@ PIC_API int pic_mlp_loss_grad(pic_ctx *ctx, const float *X, const float *y, int6
 PIC_API int pic_mlp_set_weights(pic_ctx *ctx, const float *w, int64_t n) {
     if (!ctx) return PIC_EINVAL;
     if (ctx->sticky) return ctx->sticky;
-    if (!w || (n != NPARAM && n != NPARAM + 2 * NI)) return ctx->fail(PIC_EINVAL, "expected nparam or nparam+32 floats");
+    if (!w || (n != NPARAM && n != NPARAM + 2 * NI && n != NPARAM + 2 * NI + 5))
+        return ctx->fail(PIC_EINVAL, "expected nparam, nparam+32 or nparam+37 floats");
+    if (n == NPARAM + 2 * NI + 5 && !(w[NPARAM + 2 * NI + 1] > 0.f))
+        return ctx->fail(PIC_EINVAL, "target std must be positive");
     int rc;
     if ((rc = mlp_ensure(ctx, 1))) return rc;
     MlpState &M = *ctx->mlp;
-    if (n == NPARAM + 2 * NI) {
+    if (n >= NPARAM + 2 * NI) {
         for (int i = 0; i < NI; ++i) {
             M.h_mean[i] = w[NPARAM + i];
-            M.h_std[i] = w[NPARAM + NI + i] > 0.f ? w[NPARAM + NI + i] : 1.f;
+            M.h_std[i] = w[NPARAM + NI + i] > 0.f ? w[NPARAM + NI + i] : 0.f;
         }
+    }
+    M.ymean = 0.f;
+    M.ystd = 1.f;
+    M.ymin = 1.f;
+    M.ymax = 0.f;
+    M.base = 0.f;
+    if (n == NPARAM + 2 * NI + 5) {
+        M.ymean = w[NPARAM + 2 * NI];
+        M.ystd = w[NPARAM + 2 * NI + 1];
+        M.ymin = w[NPARAM + 2 * NI + 2];
+        M.ymax = w[NPARAM + 2 * NI + 3];
+        M.base = w[NPARAM + 2 * NI + 4] != 0.f ? 1.f : 0.f;
     }
     MLPC(hipMemcpyAsync(M.P, w, 4 * NPARAM, hipMemcpyHostToDevice, ctx->st));
     if ((rc = mlp_upload_norm(ctx))) return rc;
@@ -570,6 +648,13 @@ PIC_API int pic_mlp_get_weights(pic_ctx *ctx, float *w, int64_t n) {
     for (int i = 0; i < NI; ++i) {
         w[NPARAM + i] = M.h_mean[i];
         w[NPARAM + NI + i] = M.h_std[i];
+    }
+    if (n >= NPARAM + 2 * NI + 5) {
+        w[NPARAM + 2 * NI] = M.ymean;
+        w[NPARAM + 2 * NI + 1] = M.ystd;
+        w[NPARAM + 2 * NI + 2] = M.ymin;
+        w[NPARAM + 2 * NI + 3] = M.ymax;
+        w[NPARAM + 2 * NI + 4] = M.base;
     }
     return PIC_OK;
 }

@@ -112,12 +112,13 @@ Geom pic_ctx::geom() const {
 }
 
 void pic_ctx::drop_graphs() {
-    for (auto &row : gexec)
-        for (auto &e : row)
-            if (e) {
-                (void)hipGraphExecDestroy(e);
-                e = nullptr;
-            }
+    for (auto &plane : gexec)
+        for (auto &row : plane)
+            for (auto &e : row)
+                if (e) {
+                    (void)hipGraphExecDestroy(e);
+                    e = nullptr;
+                }
 }
 
 // Builds the tile table for the current tuning and (re)allocates the sort
@@ -139,7 +140,9 @@ int pic_ctx::build_tiles() {
             for (int ty = 0; ty < nt[3 * b + 1]; ++ty)
                 for (int tx = 0; tx < nt[3 * b]; ++tx)
                     tiles.push_back({boxes[b].lo[0] + tx * T[0], boxes[b].lo[1] + ty * T[1],
-                                     boxes[b].lo[2] + tz * T[2], b});
+                                     boxes[b].lo[2] + tz * T[2], b,
+                                     pack_cell(boxes[b].lo[0], boxes[b].lo[1], boxes[b].lo[2]),
+                                     pack_cell(boxes[b].hi[0] - 1, boxes[b].hi[1] - 1, boxes[b].hi[2] - 1)});
     }
     ntiles = off[nb];
     h_box_tile_off = off;
@@ -220,6 +223,7 @@ GpdLaunch pic_ctx::gpd_args() const {
     }
     L.cycles = d_cycles;
     L.rtc = d_rtc;
+    L.bmap = d_bmap;
     L.slow = d_slow;
     L.jdirty = d_jdirty[jcur];
     L.mode = mode;
@@ -321,33 +325,40 @@ int pic_ctx::yee_half() {
     return PIC_OK;
 }
 
+// In graph mode every step is one graph launch: a step that starts with the
+// periodic particle sort (and work-queue rebuild) replays a graph captured
+// with the sort in it.
 int pic_ctx::step(int nsteps) {
     for (int i = 0; i < nsteps; ++i) {
         if (int rc = yee_half()) return rc;
-        if (steps_since_sort >= std::max(1, tun.sort_interval)) {
-            int rc;
-            if ((rc = time_begin(2))) return rc;
-            if ((rc = sort_now())) return rc;
-            if ((rc = time_end())) return rc;
-        }
+        const bool do_sort = steps_since_sort >= std::max(1, tun.sort_interval);
         if (use_graph) {
-            hipGraphExec_t &ge = gexec[jcur][pcur];
+            hipGraphExec_t &ge = gexec[do_sort ? 1 : 0][jcur][pcur];
             if (!ge) {
                 hipGraph_t gr;
                 capturing = true;
                 HIPC(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                int rc = enqueue_step();
+                int rc = do_sort ? sort_now() : PIC_OK;  // flips pcur
+                if (!rc) rc = enqueue_step();
                 hipError_t e2 = hipStreamEndCapture(st, &gr);
                 capturing = false;
                 if (rc) return rc;
                 HIPC(e2);
                 HIPC(hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0));
                 HIPC(hipGraphDestroy(gr));
+            } else if (do_sort) {
+                pcur = 1 - pcur;
+                steps_since_sort = 0;
             }
             HIPC(hipGraphLaunch(ge, st));
         } else {
-            int rc = enqueue_step();
-            if (rc) return rc;
+            int rc;
+            if (do_sort) {
+                if ((rc = time_begin(2))) return rc;
+                if ((rc = sort_now())) return rc;
+                if ((rc = time_end())) return rc;
+            }
+            if ((rc = enqueue_step())) return rc;
         }
         jcur = 1 - jcur;
         ++steps_since_sort;
@@ -655,6 +666,17 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
         h2d(c->d_boxes6, b6.data(), sizeof(int) * b6.size()) ||
         h2d(c->d_coarse_box, coarse.data(), sizeof(int) * coarse.size()))
         return init_fail(c, PIC_EDEVICE, "hipMemcpy of box tables failed");
+    {
+        BoxMap bm;
+        bm.boxes6 = c->d_boxes6;
+        bm.coarse_box = c->d_coarse_box;
+        for (int d = 0; d < 3; ++d) {
+            bm.g[d] = c->g[d];
+            bm.cg[d] = c->cg[d];
+        }
+        if ((rc = c->dalloc((void **)&c->d_bmap, sizeof(BoxMap)))) return init_fail(c, rc, "");
+        if (h2d(c->d_bmap, &bm, sizeof(BoxMap))) return init_fail(c, PIC_EDEVICE, "hipMemcpy of the box map failed");
+    }
     if ((rc = c->build_tiles())) return init_fail(c, rc, "");
 
     // fields: E = J = 0, B = b_ext (stored as B - b_ext: the uniform part is

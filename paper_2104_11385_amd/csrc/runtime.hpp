@@ -44,7 +44,8 @@ struct pic_ctx {
     int mode = PIC_LAUNCH_PERSISTENT;
     bool use_graph = false;
     bool capturing = false;
-    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // captured steps, by [sort first][field buffer][particle buffer]
+    hipGraphExec_t gexec[2][2][2] = {};
     int steps_since_sort = 0;
     int64_t step_no = 0;
 
@@ -55,6 +56,7 @@ struct pic_ctx {
     int *d_coarse_box = nullptr, *d_box_lo = nullptr, *d_box_hi = nullptr, *d_boxes6 = nullptr;
     int *d_box_nt = nullptr, *d_box_tile_off = nullptr;
     pb::TileDesc *d_tiles = nullptr;
+    pb::BoxMap *d_bmap = nullptr;
 
     // state
     pb::ParticlesRaw P[2];

@@ -389,7 +389,7 @@ class PicContext:
         self._c(lib().pic_mlp_set_weights(self.h, _ptr(w), len(w)))
 
     def mlp_get_weights(self):
-        w = np.zeros(mlp_nparam() + 32, dtype=np.float32)
+        w = np.zeros(mlp_nparam() + 37, dtype=np.float32)
         self._c(lib().pic_mlp_get_weights(self.h, _ptr(w), len(w)))
         return w
 

@@ -94,3 +94,54 @@ def normwise(a, b):
     den = np.abs(b).max()
     num = np.abs(a - b).max()
     return 0.0 if den == 0 and num == 0 else num / max(den, 1e-300)
+
+
+def u_floor(wl, e_max, nsteps):
+    """Per species: |q| dt nsteps max|E| / m, the momentum the strongest
+    electric field of the run can give a particle of that species over the
+    run.  A particle near rest has a momentum made of such impulses, each
+    carrying the rounding of the field it came from, so its momentum error
+    is measured against this scale rather than against its own |u|."""
+    return np.array([abs(s.charge) * wl.dt * nsteps * e_max / s.mass for s in wl.species])
+
+
+def check_u_per_particle(gu, ou, sp, ids, floors, tol, what=""):
+    """|u_gpu - u_oracle| <= tol * max(|u_oracle|, floor of its species), for
+    every particle (vector norms); names the worst particle on failure."""
+    du = np.linalg.norm(np.asarray(gu) - np.asarray(ou), axis=1)
+    uu = np.linalg.norm(np.asarray(ou), axis=1)
+    ref = np.maximum(uu, np.maximum(np.asarray(floors)[np.asarray(sp)], 1e-300))
+    rel = du / ref
+    k = int(np.argmax(rel)) if len(rel) else 0
+    assert len(rel) == 0 or rel[k] <= tol, (
+        f"{what}particle id {int(ids[k])} of species {int(sp[k])}: |du| = {du[k]:.3e}, |u| = {uu[k]:.3e}, "
+        f"floor {np.asarray(floors)[int(sp[k])]:.3e}: {rel[k]:.3e} > {tol:g}; "
+        f"{int((rel > tol).sum())} particles over the bar")
+    return float(rel.max()) if len(rel) else 0.0
+
+
+def box_face_planes(boxes, n):
+    """Per dimension, the sorted coordinates of every box face (0 and n
+    included)."""
+    b = np.asarray(boxes)
+    return [np.unique(np.concatenate([b[:, d], b[:, 3 + d], [0, n[d]]])) for d in range(3)]
+
+
+def near_box_face(x, boxes, n, eps):
+    """Particles within eps of a box face plane in some dimension."""
+    near = np.zeros(len(x), bool)
+    for d, planes in enumerate(box_face_planes(boxes, n)):
+        dist = np.abs(x[:, d][:, None] - planes[None, :]).min(axis=1)
+        near |= dist < eps
+    return near
+
+
+def box_of(x, boxes):
+    """Index of the box holding each position's cell floor(x)."""
+    c = np.floor(x).astype(np.int64)
+    b = np.asarray(boxes, dtype=np.int64)
+    out = np.full(len(x), -1, np.int64)
+    for i, bb in enumerate(b):
+        m = np.all((c >= bb[:3]) & (c < bb[3:]), axis=1)
+        out[m] = i
+    return out

@@ -36,3 +36,12 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_host_cores_and_one_oracle_sample():
+    import bench
+    avail, workers = bench.host_cores()
+    assert 1 <= workers <= min(16, avail)
+    # one sample step of the all-core oracle timing (its per-process unit)
+    n, t_step, t_yee = bench._oracle_sample_step((500, 1, 4))
+    assert n == 1000 and t_step > t_yee > 0

@@ -82,19 +82,64 @@ def test_training_follows_oracle_adam_and_reduces_loss():
     loss = ctx.mlp_train(X, y, epochs=epochs, batch=batch, perm=perm, init_w=P0.astype(np.float32))
     assert loss[-1] < loss[0]
     W = ctx.mlp_get_weights()
-    mean, std = W[NP:NP + 16].astype(np.float64), W[NP + 16:].astype(np.float64)
+    mean, std = W[NP:NP + 16].astype(np.float64), W[NP + 16:NP + 32].astype(np.float64)
+    rm, rs, rlo, rhi, flag = (float(v) for v in W[NP + 32:NP + 37])
     np.testing.assert_allclose(mean, X.astype(np.float64).mean(0), rtol=1e-5, atol=1e-6)
-    # the oracle replays the same Adam steps on the standardised data
+    # the network models the residual y - ln(1 + N), N from features 0 and 1
+    base = np.log1p(np.maximum(0, np.expm1(X[:, 0].astype(np.float64))) +
+                    np.maximum(0, np.expm1(X[:, 1].astype(np.float64))))
+    res = y.astype(np.float64) - base
+    assert flag == 1.0
+    np.testing.assert_allclose([rm, rs, rlo, rhi], [res.mean(), res.std(), res.min(), res.max()], rtol=1e-5)
+    # the oracle replays the same Adam steps on the standardised data and
+    # standardised residuals
     Xs = ((X - mean.astype(np.float32)) * (1.0 / std.astype(np.float32))).astype(np.float32).astype(np.float64)
+    Ys = ((res - rm) / rs).astype(np.float32).astype(np.float64)
     P = P0.copy(); m = np.zeros(NP); v = np.zeros(NP); t = 0
     for ep in range(epochs):
         for b0 in range(0, n, batch):
             idx = perm[ep, b0:b0 + batch]
-            _, g, _ = oracle.mlp_loss_grad(P, Xs[idx], y[idx].astype(np.float64), mirror=True)
+            _, g, _ = oracle.mlp_loss_grad(P, Xs[idx], Ys[idx], mirror=True)
             t += 1
             oracle.adam(P, g, m, v, t)
     err = np.abs(W[:NP] - P).max() / np.abs(P).max()
     assert err < 2e-2, f"weights after training differ by {err:.2e}"
+    # predictions come back in units of y
+    _, _, oy = oracle.mlp_loss_grad(W[:NP].astype(np.float64), Xs[:64], np.zeros(64), mirror=True, want_grad=False)
+    want = base[:64] + rm + rs * oy
+    np.testing.assert_allclose(ctx.mlp_predict(X[:64]), want, rtol=0, atol=1e-2 * np.abs(want).max())
+
+
+def test_constant_features_and_target_range():
+    # trained where features 10 and 11 never vary, then shown boxes where
+    # they do: those inputs enter as 0 (std 0), so predictions do not move,
+    # and learned costs stay inside the training targets' range
+    from paper_2104_11385_amd import picbal as pb
+    ctx = _ctx()
+    rng = np.random.default_rng(21)
+    n = 2048
+    X = rng.normal(size=(n, 16)).astype(np.float32)
+    X[:, 10] = np.log(32.0 ** 3)
+    X[:, 11] = 2.0
+    y = (12.0 + 0.8 * X[:, 2] - 0.3 * X[:, 3]).astype(np.float32)
+    ctx.mlp_train(X, y, epochs=5, batch=256, seed=3)
+    W = ctx.mlp_get_weights()
+    assert W[NP + 16 + 10] == 0.0 and W[NP + 16 + 11] == 0.0
+    Xo = X[:100].copy()
+    Xo[:, 10] = np.log(16.0 ** 3)
+    Xo[:, 11] = 3.0
+    np.testing.assert_array_equal(ctx.mlp_predict(Xo), ctx.mlp_predict(X[:100]))
+    # the context's own boxes lie far outside these synthetic inputs: the
+    # learned costs stay finite, the residual within its training range
+    c, used = ctx.box_costs(pb.PIC_COST_LEARNED)
+    assert used == pb.PIC_COST_LEARNED
+    f = ctx.box_features().astype(np.float64)
+    n_b = np.expm1(f[:, 0]) + np.expm1(f[:, 1])
+    rlo, rhi = float(W[NP + 34]), float(W[NP + 35])
+    assert np.isfinite(c).all() and (c >= 0).all()
+    assert (c <= np.expm1(rhi + np.log1p(n_b)) * (1 + 1e-5)).all()
+    assert (c >= np.expm1(rlo + np.log1p(n_b)) * (1 - 1e-5) - 1e-6).all()
+    assert np.isfinite(ctx.mlp_predict(np.full((64, 16), 40.0, np.float32))).all()
 
 
 def test_learned_costs_fall_back_when_error_exceeds_15_percent():

@@ -1,9 +1,12 @@
 """GPU parity: the HIP path against the FP64 oracle on identical seeded inputs.
 
 Tolerances (derived from the arithmetic of each precision):
-  FP64 library vs FP64 oracle: 1e-12, relative to the largest value of each
-  quantity (positions per particle relative to max(1, |x|)).
-  FP32 library vs FP64 oracle after 10 steps: 1e-5 the same way.
+  FP64 library vs FP64 oracle: 1e-12; FP32 library vs FP64 oracle after 10
+  steps: 1e-5.  Per particle: |dx| (minimal image) <= tol max(1, |x|) and
+  |du| <= tol max(|u|, u_floor), with u_floor = |q| dt steps max|E| / m per
+  species (the momentum the strongest field of the run can impart; a
+  particle near rest is held to the rounding of the impulses its momentum is
+  made of).  Fields norm-wise per component (J vanishes at many nodes).
 Every case spans several tiles and boxes; particle orders are matched by id.
 """
 import numpy as np
@@ -11,8 +14,8 @@ import pytest
 
 import oracle
 import picsynth
-from tests._util import (gpu_particles, make_ctx, min_image, normwise, oracle_steps, order_by_species_id,
-                         set_state)
+from tests._util import (box_of, check_u_per_particle, gpu_particles, make_ctx, min_image, near_box_face, normwise,
+                         oracle_steps, order_by_species_id, set_state, u_floor)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,12 +35,8 @@ def compare(ctx, wl, x, u, w, sp, ids, F, nsteps, tol, check_fields=True):
     np.testing.assert_array_equal(gsp, osp)
     dx = np.abs(min_image(gx - ox, wl.n))
     assert (dx <= tol * np.maximum(1.0, np.abs(ox))).all(), f"max |dx| = {dx.max():.3e}"
-    for s in range(len(wl.species)):
-        m = gsp == s
-        if m.sum() == 0:
-            continue
-        err = normwise(gu[m], ou[m])
-        assert err <= tol, f"species {s}: u error {err:.3e}"
+    e_max = max(np.abs(F[0:3]).max(), np.abs(OF[0:3]).max())
+    check_u_per_particle(gu, ou, gsp, gids, u_floor(wl, e_max, nsteps), tol)
     if check_fields:
         GF = ctx.get_fields()
         for c in range(9):
@@ -88,6 +87,23 @@ def test_launch_modes_agree_with_oracle(mode, graph):
     x, u, w, ids, sp, F = set_state(ctx, wl, F0)
     ctx.step(7)
     compare(ctx, wl, x, u, w, sp, ids, F, 7, TOL[8])
+
+
+@pytest.mark.parametrize("precision,mode", [(8, 2), (4, 2), (8, 0)])
+def test_graph_replay_across_sorts(precision, mode):
+    # every step one graph launch, with the particle sort and the work-queue
+    # rebuild captured into the graphs of the steps that start with them:
+    # sorts before steps 4, 7, 10 and 13; the graph of step 4 (field buffer
+    # 1, particle buffer 0) is replayed at step 10, that of step 7 at step 13
+    wl = quad_workload(precision, seed=9)
+    print(f"[parity] graph replay across sorts, precision={precision} mode={mode}", flush=True)
+    ctx = make_ctx(wl, load=False)
+    ctx.set_tuning(sort_interval=3)
+    ctx.set_launch_mode(mode, True)
+    F0 = picsynth.random_fields(wl.n, 8, amp=0.03)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+    ctx.step(14)
+    compare(ctx, wl, x, u, w, sp, ids, F, 14, TOL[precision])
 
 
 @pytest.mark.parametrize("precision,order", [(8, 2), (4, 2), (8, 3), (4, 1)])
@@ -221,15 +237,28 @@ def test_box_counts_after_steps(precision):
     got = ctx.box_counts()
     ox, ou, _ = oracle_steps(wl, x, u, w, sp, F, 10)
     want = oracle.box_counts(wl.boxes, ox, sp, len(wl.species))
+    assert got.sum() == len(x)
+    # the library's counts are those of its own particles' cells, exactly
+    gx, _, gids, gsp = gpu_particles(ctx, wl)
+    np.testing.assert_array_equal(got, oracle.box_counts(wl.boxes, gx, gsp, len(wl.species)))
     if precision == 8:
         np.testing.assert_array_equal(got, want)
-    else:
-        # a count may differ only for particles the oracle places within 1e-5
-        # of a box face
-        frac = ox - np.floor(ox)
-        near = ((frac < 1e-5) | (frac > 1 - 1e-5)).any(axis=1)
-        assert np.abs(got - want).sum() <= 2 * near.sum()
-    assert got.sum() == len(x)
+        return
+    # FP32: a particle may sit in another box than the oracle's only if the
+    # oracle places it within 1e-5 of a box face; those particles are listed
+    ox_, _, oids, osp = order_by_species_id(ox, ou, ids, sp)
+    np.testing.assert_array_equal(gids, oids)
+    differ = box_of(gx, wl.boxes) != box_of(ox_, wl.boxes)
+    near = near_box_face(ox_, wl.boxes, wl.n, 1e-5)
+    listed = [(int(s_), int(i)) for s_, i in zip(osp[differ], oids[differ])]
+    print(f"particles in another box than the oracle's: {listed}; within 1e-5 of a box face: "
+          f"{int(near.sum())}", flush=True)
+    assert not (differ & ~near).any(), f"box mismatches away from box faces: {listed}"
+    # the counts then differ exactly by those particles
+    moved = np.zeros_like(got)
+    np.add.at(moved, (box_of(gx, wl.boxes)[differ], gsp[differ]), 1)
+    np.add.at(moved, (box_of(ox_, wl.boxes)[differ], osp[differ]), -1)
+    np.testing.assert_array_equal(got - want, moved)
 
 
 @pytest.mark.parametrize("precision", [8, 4])
