@@ -210,6 +210,18 @@ PIC_API int pic_box_counts(pic_ctx *ctx, int64_t *counts);
 PIC_API int pic_get_particles_by_id(pic_ctx *ctx, int32_t species, const int64_t *ids, int64_t n, double *x3,
                                     double *u3, int32_t *found);
 
+/* The same lookup for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid allocation): no
+ * hipMalloc or hipFree, and no other allocating call.  Its scratch is one
+ * statically sized device array per GPU (5.5 MiB, held until the process
+ * ends), whose address pic_init takes once per device.  n <= 65536, else
+ * PIC_EINVAL; ids must be >= 0 and distinct (a repeated id -> PIC_EINVAL,
+ * after the outputs were written).  Every call on a GPU uses that GPU's one
+ * array: calls that overlap on one GPU (other threads, other contexts) race
+ * and must be serialised by the caller.  Synchronises. */
+PIC_API int pic_get_particles_by_id_noalloc(pic_ctx *ctx, int32_t species, const int64_t *ids, int64_t n,
+                                            double *x3, double *u3, int32_t *found);
+
 /* Copies species s's particles to caller arrays sized by *n_inout; on return
  * *n_inout is the particle count (PIC_ECAPACITY if the arrays are too small;
  * the count is still written).  Order is unspecified; ids identify

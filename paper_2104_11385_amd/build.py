@@ -17,7 +17,7 @@ INC = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpicbal.so")
 
-HIP_SOURCES = ["gpd.hip", "pic_kernels.hip", "runtime.hip", "mlp.hip"]
+HIP_SOURCES = ["gpd.hip", "pic_kernels.hip", "runtime.hip", "mlp.hip", "noalloc.hip"]
 # gpd_inst.hip is compiled once per (precision, shape order) kernel group
 GPD_GROUPS = [(real, order) for real in ("float", "double") for order in (1, 2, 3)]
 HOST_SOURCES = ["lb.cpp"]

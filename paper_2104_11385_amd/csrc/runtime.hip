@@ -574,6 +574,10 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
         return init_fail(c, PIC_EDEVICE, "no HIP device");
     (void)hipGetDeviceProperties(&prop, c->dev);
     c->n_cu = prop.multiProcessorCount;
+    {
+        std::string serr;
+        if (int rc0 = pb_noalloc_setup(c->dev, serr)) return init_fail(c, rc0, serr);
+    }
     if (hip_stream) {
         c->st = (hipStream_t)hip_stream;
         c->own_stream = false;

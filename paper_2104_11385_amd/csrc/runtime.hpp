@@ -18,6 +18,10 @@ namespace pb {
 struct MlpState;
 }
 
+// Takes the device address of the no-allocation lookup's scratch array on
+// device dev (current), once per device (noalloc.hip).
+int pb_noalloc_setup(int dev, std::string &err);
+
 struct pic_ctx {
     // problem
     int n[3] = {0, 0, 0};

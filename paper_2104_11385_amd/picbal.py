@@ -98,6 +98,7 @@ def lib():
             "pic_set_cost_timer": (ctypes.c_int, [P, i32]),
             "pic_set_staging": (ctypes.c_int, [P, i32]),
             "pic_get_particles_by_id": (ctypes.c_int, [P, i32, P, i64, P, P, P]),
+            "pic_get_particles_by_id_noalloc": (ctypes.c_int, [P, i32, P, i64, P, P, P]),
             "pic_kernel_timing": (ctypes.c_int, [P, i32]),
             "pic_kernel_times": (ctypes.c_int, [P, P, P]),
             "pic_slow_path_count": (ctypes.c_int, [P, P]),
@@ -118,7 +119,7 @@ def exported_symbols():
             "pic_get_particles", "pic_set_particles", "pic_get_field", "pic_set_field", "lb_distribute",
             "lb_efficiency", "lb_should_adopt", "lb_morton_key", "lb_comm_volume", "pic_box_features", "pic_mlp_nparam",
             "pic_mlp_train", "pic_mlp_predict", "pic_mlp_loss_grad", "pic_mlp_set_weights",
-            "pic_mlp_get_weights", "pic_set_cost_timer", "pic_set_staging", "pic_get_particles_by_id", "pic_kernel_timing", "pic_kernel_times", "pic_slow_path_count",
+            "pic_mlp_get_weights", "pic_set_cost_timer", "pic_set_staging", "pic_get_particles_by_id", "pic_get_particles_by_id_noalloc", "pic_kernel_timing", "pic_kernel_times", "pic_slow_path_count",
             "pic_strerror", "pic_last_error"]
 
 
@@ -343,6 +344,16 @@ class PicContext:
         n = len(ids)
         x = np.zeros((n, 3)); u = np.zeros((n, 3)); found = np.zeros(n, dtype=np.int32)
         self._c(lib().pic_get_particles_by_id(self.h, int(species), _ptr(ids), n, _ptr(x), _ptr(u), _ptr(found)))
+        return x, u, found.astype(bool)
+
+    def get_particles_by_id_noalloc(self, species, ids):
+        """As get_particles_by_id, through the entry point that allocates no
+        device memory (at most 65,536 ids per call)."""
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        n = len(ids)
+        x = np.zeros((n, 3)); u = np.zeros((n, 3)); found = np.zeros(n, dtype=np.int32)
+        self._c(lib().pic_get_particles_by_id_noalloc(self.h, int(species), _ptr(ids), n, _ptr(x), _ptr(u),
+                                                      _ptr(found)))
         return x, u, found.astype(bool)
 
     def set_staging(self, enable=True):
