@@ -451,6 +451,17 @@ struct PState {
             P.u[d][p] = u[d];
         }
     }
+    // A stand-in for a lane past the item's end: a particle of zero weight
+    // at rest at the tile origin, whose current and queue entries vanish.
+    __device__ __forceinline__ void blank(uint32_t origin) {
+        cell = origin;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            f[d] = (real)0.25;
+            u[d] = (real)0;
+        }
+        w = (real)0;
+    }
     __device__ __forceinline__ void settle() const {
         asm volatile("" : : "v"(cell));
 #pragma unroll
@@ -472,7 +483,7 @@ struct Deferred {
 };
 
 template <typename real, int M, int TX, int TY, int TZ, int H, bool R>
-__device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, const PState<real> &ps,
+__device__ __forceinline__ void push_particle(const GpdArgs<real> &A, bool live, const PState<real> &ps,
                                               const TileDesc &td, real hq, real cq, const real *sEB, double *sJ,
                                               unsigned &nslow, Deferred<real> &df, PState<real> &out) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
@@ -522,7 +533,7 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
             acc.r[d] = ref[d];
         }
         gather6<real, M>(acc, GW, EB);
-        ++nslow;
+        nslow += live;  // stand-ins past the item's end do not count
     }
     // the arrays hold B minus its uniform external part (whose curl is zero)
     EB[3] += A.bext[0];
@@ -548,17 +559,18 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
     real coef = cq * w;
     bool moved = leaves_ref<real, M>(d0[0], D[0]) || leaves_ref<real, M>(d0[1], D[1]) ||
                  leaves_ref<real, M>(d0[2], D[2]);
+    // every lane's record is complete (finite values), whatever path it takes
+    df.rel = (rel[0] + 8) | ((rel[1] + 8) << 8) | ((rel[2] + 8) << 16);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        df.d0[d] = d0[d];
+        df.D[d] = D[d];
+    }
+    df.coef = coef;
     if (fast) {
         if (moved || R) {
             df.want = moved;
             df.keep = !moved;
-            df.rel = (rel[0] + 8) | ((rel[1] + 8) << 8) | ((rel[2] + 8) << 16);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                df.d0[d] = d0[d];
-                df.D[d] = D[d];
-            }
-            df.coef = coef;
         } else {
             DepW<real, M> DW[3];
 #pragma unroll
@@ -566,7 +578,7 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
             LdsJ<real, C> acc{sJ, (rel[0] + H + C::RL_J) + C::JX * ((rel[1] + H + C::RL_J) + C::JY * (rel[2] + H + C::RL_J)), 0};
             deposit3<real, M, M + 1>(acc, DW, coef);
         }
-    } else {
+    } else if (live) {
         DepW<real, M> DW[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) DW[d].set(d0[d], D[d]);
@@ -581,27 +593,22 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, int p, con
         deposit3<real, M, M + 2>(acc, DW, coef);
     }
 
-    // new canonical position: cell + offset in [0, 1), periodic wrap
+    // new canonical position: cell + offset in [0, 1), periodic wrap (a
+    // step below zero so small that x + 1 rounds to 1 keeps the cell, at
+    // offset 0); selects rather than branches
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        real x = f[d] + D[d];
-        int k = 0;
-        if (x < (real)0) {
-            x += (real)1;
-            k = -1;
-            if (x >= (real)1) {
-                x = (real)0;
-                k = 0;
-            }
-        } else if (x >= (real)1) {
-            x -= (real)1;
-            k = 1;
-        }
+        const real x = f[d] + D[d];
+        const bool lo = x < (real)0, hi = x >= (real)1;
+        real y = lo ? x + (real)1 : (hi ? x - (real)1 : x);
+        int k = lo ? -1 : (hi ? 1 : 0);
+        const bool stay = lo && y >= (real)1;
+        y = stay ? (real)0 : y;
+        k = stay ? 0 : k;
         int cc = c[d] + k;
-        if (cc < 0) cc += A.n[d];
-        else if (cc >= A.n[d]) cc -= A.n[d];
+        cc = cc < 0 ? cc + A.n[d] : (cc >= A.n[d] ? cc - A.n[d] : cc);
         c[d] = cc;
-        f[d] = x;
+        f[d] = y;
     }
     out.cell = pack_cell(c[0], c[1], c[2]);
 #pragma unroll
@@ -705,9 +712,11 @@ __device__ __forceinline__ void deposit_runs(const Deferred<real> &df, double *s
     const bool keep = df.keep;
     RowRuns<real> rr;
     rr.set(keep ? df.rel : -1 - (int)__lane_id());
+    // a lane whose particle changed node contributes nothing here (its
+    // offsets and displacement are finite, its charge factor is zeroed)
     DepW<real, M> DW[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) DW[d].set_kept(keep ? df.d0[d] : (real)0, keep ? df.D[d] : (real)0);
+    for (int d = 0; d < 3; ++d) DW[d].set_kept(df.d0[d], df.D[d]);
     const real coef = keep ? df.coef : (real)0;
     const int pk = df.rel;
     const int r0 = (pk & 255) - 8, r1 = ((pk >> 8) & 255) - 8, r2 = ((pk >> 16) & 255) - 8;
@@ -732,6 +741,7 @@ __device__ __forceinline__ void note_foreign(const BoxMap &bm, uint32_t cell, in
     int x, y, z;
     unpack_cell(cell, x, y, z);
     const int b = bm.coarse_box[(x / bm.g[0]) + bm.cg[0] * ((y / bm.g[1]) + bm.cg[1] * (z / bm.g[2]))];
+#pragma unroll 1
     for (int k = 0; k < kForeignSlots; ++k) {
         const int slot = (b + k) & (kForeignSlots - 1);
         const int prev = atomicCAS(&sbox[slot], -1, b);
@@ -754,6 +764,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     __shared__ unsigned long long sCyc, sRtc;
     __shared__ unsigned int sSlow;
     __shared__ int sItem[3];
+    __shared__ real sSpc[2 * kMaxSpecies];  // per species: q dt / (2 m), -q / dt
     __shared__ int sQn[8];  // queue lengths of the block's waves at the end of an item
     // particles of the item whose cell lies outside the tile's box (they
     // drifted across a box face since the last sort), counted per box
@@ -770,6 +781,10 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
 
     // the J window starts clear; each flush clears what it reads
     for (int i = tid; i < 3 * C::NJ; i += nthr) sJ[i] = 0.0;
+    if (tid < kMaxSpecies) {
+        sSpc[2 * tid] = A.h[tid];
+        sSpc[2 * tid + 1] = A.coefq[tid];
+    }
     for (int iter = 0;; ++iter) {
         int tile, pbeg, pend;
         if (tid < kForeignSlots) {
@@ -881,27 +896,25 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 bnd[k] = k + 1 < nsp ? A.segstart[tile * nsp + k + 1] : INT_MAX;
             // the next particle's loads are issued before this one is
             // computed; the trip count is the same for every lane of a wave
+            // lanes past the item's end step a zero-weight stand-in, so that
+            // every lane runs the same code without branches around it
+            const uint32_t origin = pack_cell(td.x0, td.y0, td.z0);
             PState<real> cur;
             if (sb + tid < se) cur.load(A.P, sb + tid);
+            else cur.blank(origin);
             cur.settle();
             for (int base = sb + (tid & ~63); base < se; base += nthr) {
                 const int p = base + lane;
                 PState<real> nxt;
                 if (p + nthr < se) nxt.load(A.P, p + nthr);
+                else nxt.blank(origin);
                 int sp = 0;
 #pragma unroll
                 for (int k = 0; k < kMaxSpecies - 1; ++k) sp += p >= bnd[k];
-                real hq = A.h[0], cq = A.coefq[0];
-#pragma unroll
-                for (int k = 1; k < kMaxSpecies; ++k)
-                    if (sp == k) {
-                        hq = A.h[k];
-                        cq = A.coefq[k];
-                    }
+                const real hq = sSpc[2 * sp], cq = sSpc[2 * sp + 1];
                 Deferred<real> df;
                 df.want = false;
                 df.keep = false;
-                df.rel = 0x080808;  // the tile origin, for lanes without a particle
                 if (timed) {
                     // particles that drifted out of the tile's box since the
                     // last sort are counted under the box that holds them
@@ -915,14 +928,13 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                     unpack_cell(bh, hx, hy, hz);
                     // branch-free: one ballot, and a branch only for a wave
                     // that holds such a particle
-                    const bool foreign = (p < se) & (((unsigned)(cx - lx) > (unsigned)(hx - lx)) |
-                                                     ((unsigned)(cy - ly) > (unsigned)(hy - ly)) |
-                                                     ((unsigned)(cz - lz) > (unsigned)(hz - lz)));
-                    if (__ballot(foreign) && foreign) note_foreign(*A.bmap, cur.cell, sFBox, sFCnt, sFAny);
+                    const bool foreign = ((unsigned)(cx - lx) > (unsigned)(hx - lx)) |
+                                         ((unsigned)(cy - ly) > (unsigned)(hy - ly)) |
+                                         ((unsigned)(cz - lz) > (unsigned)(hz - lz));
+                    if (foreign) note_foreign(*A.bmap, cur.cell, sFBox, sFCnt, sFAny);
                 }
                 PState<real> moved;
-                if (p < se)
-                    push_particle<real, M, TX, TY, TZ, H, R>(A, p, cur, td, hq, cq, sEB, sJ, nslow, df, moved);
+                push_particle<real, M, TX, TY, TZ, H, R>(A, p < se, cur, td, hq, cq, sEB, sJ, nslow, df, moved);
                 if constexpr (R) deposit_runs<real, M, TX, TY, TZ, H>(df, sJ);
                 const unsigned long long mask = __ballot(df.want);
                 if (mask) {
