@@ -141,6 +141,26 @@ def test_dense_nodes_both_particle_orders(precision, order, run_sum):
     compare(ctx, wl, x, u, w, sp, ids, F, 10, TOL[precision])
 
 
+@pytest.mark.parametrize("mode,graph", [(0, False), (1, False), (2, True), (0, True)])
+def test_global_path_in_every_launch_mode(mode, graph):
+    # the particles the tile kernel leaves to the global-path kernel (its
+    # list is filled by every launch of the tile kernel in the step and
+    # emptied by the global kernel) match the oracle in every launch mode,
+    # eager and replayed, across several steps
+    wl = quad_workload(4, u_th=0.6, seed=9)
+    print(f"[parity] global path mode={mode} graph={graph}", flush=True)
+    ctx = make_ctx(wl, load=False)
+    ctx.set_tuning(sort_interval=1000)
+    ctx.set_launch_mode(mode, graph)
+    F0 = picsynth.random_fields(wl.n, 3, amp=0.02)
+    x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+    ctx.slow_path_count()
+    ctx.step(8)
+    n_slow = ctx.slow_path_count()
+    assert 0 < n_slow < 8 * len(ids)
+    compare(ctx, wl, x, u, w, sp, ids, F, 8, TOL[4])
+
+
 @pytest.mark.parametrize("precision,order", [(8, 2), (4, 2), (8, 1), (4, 3)])
 def test_unstaged_reference_path(precision, order):
     # no LDS windows: every particle gathers from and deposits into the
