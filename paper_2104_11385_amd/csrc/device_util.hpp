@@ -117,6 +117,8 @@ template <int S>
 __device__ __forceinline__ int row_shl(int v) {
     return __builtin_amdgcn_update_dpp(0, v, 0x100 + S, 0xF, 0xF, true);
 }
+// Lane 16 r + 15 to the lanes of row r + 1 (rows 1-3; row 0 receives 0).
+__device__ __forceinline__ int row_bcast15(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x142, 0xE, 0xF, false); }
 template <int S>
 __device__ __forceinline__ float row_shr(float v) {
     return __int_as_float(row_shr<S>(__float_as_int(v)));
@@ -127,15 +129,30 @@ __device__ __forceinline__ double row_shr(double v) {
     const int lo = row_shr<S>((int)b), hi = row_shr<S>((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+__device__ __forceinline__ double row_bcast15(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = row_bcast15((int)b), hi = row_bcast15((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
 // Segments of equal keys in a 16-lane row (contiguous runs, keys never 0):
 // m[j] = 1 when lanes i - 2^j .. i all hold lane i's key, else 0.
+// A run that crosses one row boundary, into a row that it does not both fill
+// and leave, is then summed across it: the lanes of the run's part in the
+// later row add the sum at the earlier row's last lane (m[4] = 1), and that
+// lane stops being a leader, so that the two rows' leaders of one run do not
+// add to one LDS address in the same instruction.  A run over three rows or
+// more keeps a leader per row (a correct sum in parts).
 template <typename real>
 struct RowRuns {
-    real m[4];
-    bool last;  // lane i is the last lane of its run inside its row
+    real m[5];
+    bool last;  // lane i holds the sum of its run (or of the run's part in its row)
     __device__ __forceinline__ void set(int key) {
-        int f1 = row_shr<1>(key) == key;
+        const int lane = (int)__lane_id(), row = lane >> 4, col = lane & 15;
+        // key of the lane before, across rows too (DPP wave_shr:1)
+        const bool eq = __builtin_amdgcn_update_dpp(0, key, 0x138, 0xF, 0xF, false) == key;
+        const unsigned long long E = __ballot(eq);
+        int f1 = eq && col != 0;
         int f2 = f1 & row_shr<1>(f1);
         int f4 = f2 & row_shr<2>(f2);
         int f8 = f4 & row_shr<4>(f4);
@@ -144,14 +161,30 @@ struct RowRuns {
         m[2] = (real)f4;
         m[3] = (real)f8;
         last = row_shl<1>(key) != key;
+        // wave-uniform: lanes where a run starts inside a row, runs across
+        // the boundaries after rows 0, 1, 2, and which of them are merged
+        const unsigned long long brk = ~E & ~0x0001000100010001ull;
+        const bool c0 = (E >> 16) & 1, c1 = (E >> 32) & 1, c2 = (E >> 48) & 1;
+        const bool w1 = ((brk >> 16) & 0xFFFFull) == 0, w2 = ((brk >> 32) & 0xFFFFull) == 0;
+        const unsigned G = ((c0 && !(w1 && c1)) ? 2u : 0u) | ((c1 && !(w2 && c2)) ? 4u : 0u) | (c2 ? 8u : 0u);
+        // the lane lies in the first run of its row: no run starts in its
+        // row before it, and it starts none itself
+        const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(brk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)brk, 0u));
+        const int r1 = __popcll(brk & 0xFFFFull), r2 = __popcll(brk & 0xFFFFFFFFull), r3 = __popcll(brk & 0xFFFFFFFFFFFFull);
+        const int rowbase = row == 0 ? 0 : (row == 1 ? r1 : (row == 2 ? r2 : r3));
+        const bool initial = below == rowbase && (eq || col == 0);
+        m[4] = (real)(((G >> row) & 1u) && initial);
+        last = last && !(col == 15 && ((G >> (row + 1)) & 1u));
     }
     // Inclusive segmented sum: the last lane of each run receives the run's
-    // sum inside the row (Hillis-Steele steps 1, 2, 4, 8).
+    // sum inside the row (Hillis-Steele steps 1, 2, 4, 8), then across one
+    // row boundary.
     __device__ __forceinline__ real sum(real v) const {
         v = fma(row_shr<1>(v), m[0], v);
         v = fma(row_shr<2>(v), m[1], v);
         v = fma(row_shr<4>(v), m[2], v);
         v = fma(row_shr<8>(v), m[3], v);
+        v = fma(row_bcast15(v), m[4], v);
         return v;
     }
     // The same sum of N single-precision values, one v_fmac_f32 with a DPP
@@ -163,24 +196,26 @@ struct RowRuns {
 };
 
 // Each statement starts with two wait states: a DPP read of a VGPR written
-// by the instruction just before it needs them.
-#define PB_FMAC_STEP6(SH, v, k, m)                                                         \
+// by the instruction just before it needs them.  CTL is the whole DPP
+// control (lane pattern and masks).
+#define PB_FMAC_STEP6(CTL, v, k, m)                                                        \
     asm volatile("s_nop 1\n\t"                                                            \
-                 "v_fmac_f32_dpp %0, %0, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
-                 "v_fmac_f32_dpp %1, %1, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
-                 "v_fmac_f32_dpp %2, %2, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
-                 "v_fmac_f32_dpp %3, %3, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
-                 "v_fmac_f32_dpp %4, %4, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
-                 "v_fmac_f32_dpp %5, %5, %6 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1"     \
+                 "v_fmac_f32_dpp %0, %0, %6 " CTL "\n\t"                                   \
+                 "v_fmac_f32_dpp %1, %1, %6 " CTL "\n\t"                                   \
+                 "v_fmac_f32_dpp %2, %2, %6 " CTL "\n\t"                                   \
+                 "v_fmac_f32_dpp %3, %3, %6 " CTL "\n\t"                                   \
+                 "v_fmac_f32_dpp %4, %4, %6 " CTL "\n\t"                                   \
+                 "v_fmac_f32_dpp %5, %5, %6 " CTL                                           \
                  : "+v"(v[k]), "+v"(v[k + 1]), "+v"(v[k + 2]), "+v"(v[k + 3]), "+v"(v[k + 4]),   \
                    "+v"(v[k + 5])                                                           \
                  : "v"(m))
-#define PB_FMAC_STEP2(SH, v, k, m)                                                         \
+#define PB_FMAC_STEP2(CTL, v, k, m)                                                        \
     asm volatile("s_nop 1\n\t"                                                            \
-                 "v_fmac_f32_dpp %0, %0, %2 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
-                 "v_fmac_f32_dpp %1, %1, %2 " SH " row_mask:0xf bank_mask:0xf bound_ctrl:1"     \
+                 "v_fmac_f32_dpp %0, %0, %2 " CTL "\n\t"                                   \
+                 "v_fmac_f32_dpp %1, %1, %2 " CTL                                           \
                  : "+v"(v[k]), "+v"(v[k + 1])                                               \
                  : "v"(m))
+#define PB_ROW_SHR(S) "row_shr:" #S " row_mask:0xf bank_mask:0xf bound_ctrl:1"
 
 template <>
 template <int N>
@@ -192,14 +227,17 @@ __device__ __forceinline__ void RowRuns<float>::sum_n(float (&v)[N]) const {
         _Pragma("unroll") for (; k + 6 <= N; k += 6) PB_FMAC_STEP6(SH, v, k, mm);          \
         _Pragma("unroll") for (; k + 2 <= N; k += 2) PB_FMAC_STEP2(SH, v, k, mm);          \
     }
-    PB_FMAC_ALL("row_shr:1", m[0]);
-    PB_FMAC_ALL("row_shr:2", m[1]);
-    PB_FMAC_ALL("row_shr:4", m[2]);
-    PB_FMAC_ALL("row_shr:8", m[3]);
+    PB_FMAC_ALL(PB_ROW_SHR(1), m[0]);
+    PB_FMAC_ALL(PB_ROW_SHR(2), m[1]);
+    PB_FMAC_ALL(PB_ROW_SHR(4), m[2]);
+    PB_FMAC_ALL(PB_ROW_SHR(8), m[3]);
+    // rows 1-3 take lane 15 of the row before; row 0 is not written
+    PB_FMAC_ALL("row_bcast:15 row_mask:0xe bank_mask:0xf", m[4]);
 #undef PB_FMAC_ALL
 }
 #undef PB_FMAC_STEP6
 #undef PB_FMAC_STEP2
+#undef PB_ROW_SHR
 
 // Box, tile and cell-in-tile of global cell (x, y, z).
 __device__ __forceinline__ int box_of_cell(const Geom &G, int x, int y, int z) {

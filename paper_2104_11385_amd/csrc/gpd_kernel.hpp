@@ -599,10 +599,12 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, bool live,
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const real x = f[d] + D[d];
-        const bool lo = x < (real)0, hi = x >= (real)1;
-        real y = lo ? x + (real)1 : (hi ? x - (real)1 : x);
-        int k = lo ? -1 : (hi ? 1 : 0);
-        const bool stay = lo && y >= (real)1;
+        // |D| < 1: the floor is -1, 0 or 1, and x - floor(x) rounds as
+        // x + 1 or x - 1 would
+        const real fl = floor(x);
+        real y = x - fl;
+        int k = (int)fl;
+        const bool stay = y >= (real)1;
         y = stay ? (real)0 : y;
         k = stay ? 0 : k;
         int cc = c[d] + k;
