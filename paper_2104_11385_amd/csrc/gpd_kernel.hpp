@@ -656,9 +656,11 @@ struct RegJ {
     }
 };
 
+// One component of the run sums; lanes with lead set add where they end a
+// run (their run lies in the staged window).
 template <typename real, int M, int COMP, typename Acc>
 __device__ __forceinline__ void runs_comp(Acc &J, const DepW<real, M> DW[3], real coef, const RowRuns<real> &rr,
-                                          bool keep) {
+                                          bool lead) {
     constexpr int L = M + 1;
     RegJ<real, L> acc;
     deposit3<real, M, L, 1 << COMP>(acc, DW, coef);
@@ -691,7 +693,7 @@ __device__ __forceinline__ void runs_comp(Acc &J, const DepW<real, M> DW[3], rea
                 for (int a = 0; a < L; ++a)
                     if (RegJ<real, L>::used(COMP, a, b, c)) acc.v[COMP][a][b][c] = rr.sum(acc.v[COMP][a][b][c]);
     }
-    if (keep && rr.last) {
+    if (lead && rr.last) {
 #pragma unroll
         for (int c = 0; c < L; ++c)
 #pragma unroll
@@ -704,30 +706,31 @@ __device__ __forceinline__ void runs_comp(Acc &J, const DepW<real, M> DW[3], rea
 
 // Kept-node currents of a wave, summed over runs of neighbouring lanes that
 // share a reference node (node-major order puts a node's particles side by
-// side) and added to LDS once per run and 16-lane row.  Every lane of the
-// wave calls it; lanes without a kept particle contribute zero and break
-// runs.
+// side) and added to LDS by one leader lane per run.  Every lane of the wave
+// calls it.  A particle that changed node contributes zero here (its offsets
+// and displacement are finite, its charge factor is zeroed) but keeps its
+// place in its node's run, so that a node's run is not split in two whose
+// leaders would add to the same LDS addresses in one instruction; only
+// lanes outside the staged windows break runs.
 template <typename real, int M, int TX, int TY, int TZ, int H>
 __device__ __forceinline__ void deposit_runs(const Deferred<real> &df, double *sJ) {
     using C = Cfg<real, M, TX, TY, TZ, H>;
     constexpr int L = M + 1;
-    const bool keep = df.keep;
+    const bool inwin = df.keep || df.want;
     RowRuns<real> rr;
-    rr.set(keep ? df.rel : -1 - (int)__lane_id());
-    // a lane whose particle changed node contributes nothing here (its
-    // offsets and displacement are finite, its charge factor is zeroed)
+    rr.set(inwin ? df.rel : -1 - (int)__lane_id());
     DepW<real, M> DW[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) DW[d].set_kept(df.d0[d], df.D[d]);
-    const real coef = keep ? df.coef : (real)0;
+    const real coef = df.keep ? df.coef : (real)0;
     const int pk = df.rel;
     const int r0 = (pk & 255) - 8, r1 = ((pk >> 8) & 255) - 8, r2 = ((pk >> 16) & 255) - 8;
     LdsJ<real, C> J{sJ, (r0 + H + C::RL_J) + C::JX * ((r1 + H + C::RL_J) + C::JY * (r2 + H + C::RL_J)), 0};
     J.begin(DW[0].s, DW[1].s, DW[2].s);
     // one component at a time keeps (M+1)^2 M partial sums live
-    runs_comp<real, M, 0>(J, DW, coef, rr, keep);
-    runs_comp<real, M, 1>(J, DW, coef, rr, keep);
-    runs_comp<real, M, 2>(J, DW, coef, rr, keep);
+    runs_comp<real, M, 0>(J, DW, coef, rr, inwin);
+    runs_comp<real, M, 1>(J, DW, coef, rr, inwin);
+    runs_comp<real, M, 2>(J, DW, coef, rr, inwin);
 }
 
 // Slots of a block's table of foreign boxes: a tile and the cells its
