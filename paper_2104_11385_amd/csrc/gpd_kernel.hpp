@@ -428,27 +428,25 @@ template <typename real>
 struct PState {
     uint32_t cell;
     real f[3], u[3], w;
+    // The particle arrays are streamed once per step: their loads and stores
+    // carry the non-temporal hint, which leaves the caches to the field
+    // windows and the current.
     __device__ __forceinline__ void load(const Particles<real> &P, int p) {
-        cell = P.cell[p];
+        cell = __builtin_nontemporal_load(&P.cell[p]);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            f[d] = P.f[d][p];
-            u[d] = P.u[d][p];
+            f[d] = __builtin_nontemporal_load(&P.f[d][p]);
+            u[d] = __builtin_nontemporal_load(&P.u[d][p]);
         }
-        w = P.w[p];
+        w = __builtin_nontemporal_load(&P.w[p]);
     }
-    // Makes the registers count as used here, so the compiler waits for the
-    // loads at this point.  Used on the first particle before the loop
-    // (otherwise that path's pending loads merge into the loop's and every
-    // iteration stalls on the next particle's first load) and on the next
-    // particle before the current one's stores.
     // Writes the moved particle (cell, offsets, momentum) back to slot p.
     __device__ __forceinline__ void store(const Particles<real> &P, int p) const {
-        P.cell[p] = cell;
+        __builtin_nontemporal_store(cell, &P.cell[p]);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            P.f[d][p] = f[d];
-            P.u[d][p] = u[d];
+            __builtin_nontemporal_store(f[d], &P.f[d][p]);
+            __builtin_nontemporal_store(u[d], &P.u[d][p]);
         }
     }
     // A stand-in for a lane past the item's end: a particle of zero weight
@@ -462,6 +460,11 @@ struct PState {
         }
         w = (real)0;
     }
+    // Makes the registers count as used here, so the compiler waits for the
+    // loads at this point.  Used on the first particle before the loop
+    // (otherwise that path's pending loads merge into the loop's and every
+    // iteration stalls on the next particle's first load) and on the next
+    // particle before the current one's stores.
     __device__ __forceinline__ void settle() const {
         asm volatile("" : : "v"(cell));
 #pragma unroll
