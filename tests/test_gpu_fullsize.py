@@ -122,6 +122,81 @@ def test_c2_one_step_sampled_against_oracle():
         assert err <= TOL * scale, f"component {comp}: max error {err:.3e} against scale {scale:.3e}"
 
 
+def test_c2_sampled_step_at_the_end_of_a_sort_interval():
+    # The 20th step after a sort (the last before the next one): over 19
+    # steps ~7% of the particles a step have changed node while keeping
+    # their slots, so the node runs of the lane sums are at their most cut up
+    # (a node's run broken by particles of other nodes, one node in several
+    # runs of a row).  The oracle steps the library's own state after step 19
+    # once: every particle within reach of the sampled cells, and sampled
+    # particles of both species.
+    import bench
+    import oracle
+    from paper_2104_11385_amd import picbal as pb
+
+    wl = bench.workload()
+    n = np.array(wl.n)
+    print("full-size parity: c2, persistent + graph, step 20 after a sort", flush=True)
+    rng = np.random.default_rng(12)
+    lo = np.array(wl.species[0].region_lo)
+    hi = np.array(wl.species[0].region_hi)
+    cells = [tuple(int(v) for v in rng.integers(lo, hi)) for _ in range(10)]
+    cells += [(0, 17, 121), (255, 40, 122), (63, 9, 130), (64, 200, 119), (100, 63, 127), (31, 64, 128)]
+    cz = np.array([c[2] for c in cells]); cy = np.array([c[1] for c in cells]); cx = np.array([c[0] for c in cells])
+    ctx = bench.make_ctx(wl)
+    try:
+        ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, True)
+        ctx.set_fields(picsynth.random_fields(tuple(n), 7, amp=0.03))
+        ctx.step(19)
+        ctx.sync()
+        F = np.ascontiguousarray(ctx.get_fields())
+        xs, us, ws, sps, samples = [], [], [], [], []
+        for s in range(len(wl.species)):
+            x, u, w, ids = ctx.get_particles(s)
+            c = np.floor(x).astype(np.int64)
+            near = np.zeros(len(w), bool)
+            for cell in cells:
+                d = np.abs(c - np.array(cell))
+                near |= np.all(np.minimum(d, n - d) <= REACH, axis=1)
+            smp = np.sort(rng.choice(len(w), 2000, replace=False))
+            keep = np.union1d(np.nonzero(near)[0], smp)
+            xs.append(x[keep]); us.append(u[keep]); ws.append(w[keep]); sps.append(np.full(len(keep), s, np.int32))
+            samples.append((ids[smp], np.searchsorted(keep, smp)))
+            del x, u, w, ids, c, near
+        ctx.step(1)
+        ctx.sync()
+        got_cells = np.stack([ctx.get_field(c)[cz, cy, cx] for c in range(9)])
+        got = [ctx.get_particles_by_id(s, samples[s][0]) for s in range(len(wl.species))]
+    finally:
+        ctx.finalize()
+
+    off = np.cumsum([0] + [len(w) for w in ws])
+    x = np.ascontiguousarray(np.concatenate(xs)); u = np.ascontiguousarray(np.concatenate(us))
+    w = np.concatenate(ws); sp = np.concatenate(sps)
+    u0 = u.copy()
+    q = np.array([s.charge for s in wl.species]); mass = np.array([s.mass for s in wl.species])
+    F0 = F.copy()
+    oracle.pic_step(wl.order, tuple(n), wl.dt, x, u, w, sp, q, mass, F, 1)
+    e_max = max(np.abs(F0[0:3]).max(), np.abs(F[0:3]).max())
+    for s in range(len(wl.species)):
+        gx, gu, found = got[s]
+        assert found.all()
+        k = off[s] + samples[s][1]
+        d = np.abs(gx - x[k])
+        d = np.minimum(d, n - d)
+        assert d.max() <= TOL, f"species {s}: max |dx| = {d.max():.3e}"
+        # momenta against the step's own impulse scale (the particles start
+        # from the library's state, so one step's rounding is what differs)
+        check_u_per_particle(gu, u[k], np.full(len(k), s), samples[s][0], u_floor(wl, e_max, 1), TOL)
+        assert np.abs(u[k] - u0[k]).max() > 0
+    want = F[:, cz, cy, cx]
+    for comp in range(9):
+        scale = max(np.abs(want[comp]).max(), np.abs(F0[comp]).max(), 1e-30)
+        err = np.abs(got_cells[comp] - want[comp]).max()
+        assert err <= TOL * scale, f"component {comp}: max error {err:.3e} against scale {scale:.3e}"
+    assert np.abs(want[6:9]).max() > 0
+
+
 def _ids_of_cells(wl, s, cells):
     """Ids of species s whose initial cell is one of `cells` ([k, 3])."""
     sp = wl.species[s]
