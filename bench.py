@@ -207,9 +207,12 @@ def run_gpu(args):
                    "loaded_boxes": int(loaded.sum()),
                    "cv_loaded": float(costs[loaded].std() / costs[loaded].mean()) if loaded.any() else None}
     # overhead of the device-timer counters: gather-push-deposit kernel time
-    # with the counters on and off, alternated three times
+    # with the counters on and off, alternated three times; each leg times
+    # two whole sort intervals, since the kernel slows from one sort to the
+    # next (the node runs loosen) and legs at different phases of the
+    # interval would differ by more than the counters cost
     on_ms, off_ms = [], []
-    nsteps = max(10, args.steps // 4)
+    nsteps = 2 * max(1, tun.sort_interval)
     for _ in range(3):
         for flag, acc in ((True, on_ms), (False, off_ms)):
             ctx.set_cost_timer(flag)
@@ -219,12 +222,13 @@ def run_gpu(args):
     timer_stats["gpd_ms_timer_on"] = float(np.median(on_ms))
     timer_stats["gpd_ms_timer_off"] = float(np.median(off_ms))
     timer_stats["overhead"] = float(np.median(on_ms) / np.median(off_ms) - 1.0)
+    timer_stats["steps_per_leg"] = nsteps
     # the unstaged reference: every particle gathers from and deposits into
     # global memory directly (no LDS windows), same launch mode
     unstaged = None
     if not args.no_unstaged:
         ctx.set_staging(False)
-        un_step, un_k, un_n = timed(mode, False, nsteps, 2, True)
+        un_step, un_k, un_n = timed(mode, False, max(10, args.steps // 4), 2, True)
         ctx.set_staging(True)
         ctx.slow_path_count()
         unstaged = {"ms_per_step": un_step, "gpd_ms": un_k[0] / max(1, un_n[0]),
