@@ -17,9 +17,9 @@
 // window that it adds to the global J at the end of the item.  Each wave
 // walks its own 64-particle runs of the item.  With R (node-major particle
 // order), the currents of lanes whose particles keep a common reference node
-// are summed across the lanes of each 16-lane row before one LDS add per
-// run; particles that change node wait in a per-wave queue for a wider
-// deposit on full waves.
+// are summed across the lanes of each 16-lane row (and across one row
+// boundary) before one LDS add per run; particles that change node wait in a
+// per-wave queue for a wider deposit on full waves.
 #pragma once
 
 #include "device_util.hpp"
