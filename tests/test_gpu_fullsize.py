@@ -53,16 +53,21 @@ def _neighbourhood_ids(wl, s, cells):
     return np.unique(np.concatenate(ids)) if ids else np.zeros(0, np.int64)
 
 
-def test_c2_one_step_sampled_against_oracle():
+@pytest.mark.parametrize("precision", [4, 8])
+def test_c2_one_step_sampled_against_oracle(precision):
+    # FP32 (the benchmark) at the workload's bar; FP64 (the same kernel
+    # compiled in double, two waves per SIMD) at the FP64 bar, 1e-12
     import bench
     import oracle
     from paper_2104_11385_amd import picbal as pb
 
     wl = bench.workload()
+    wl.precision = precision
+    tol = TOL if precision == 4 else 1e-12
     n = tuple(wl.n)
-    print("full-size parity: c2, persistent + graph, 1 step", flush=True)
+    print(f"full-size parity: c2, precision {precision}, persistent + graph, 1 step", flush=True)
     F0 = picsynth.random_fields(n, 7, amp=0.03)
-    ctx = bench.make_ctx(wl)
+    ctx = bench.ctx_for(wl)
     try:
         ctx.set_launch_mode(pb.PIC_LAUNCH_PERSISTENT, True)
         ctx.set_fields(F0)
@@ -107,9 +112,9 @@ def test_c2_one_step_sampled_against_oracle():
         px, pu = gx[where[samples[s]]], gu[where[samples[s]]]
         d = np.abs(px - ox)
         d = np.minimum(d, np.array(n) - d)             # periodic images
-        assert d.max() <= TOL, f"species {s}: max |dx| = {d.max():.3e}"
+        assert d.max() <= tol, f"species {s}: max |dx| = {d.max():.3e}"
         e_max = max(np.abs(F0[0:3]).max(), np.abs(F[0:3]).max())
-        check_u_per_particle(pu, ou, np.full(len(ou), s), samples[s], u_floor(wl, e_max, 1), TOL)
+        check_u_per_particle(pu, ou, np.full(len(ou), s), samples[s], u_floor(wl, e_max, 1), tol)
         off += len(ids)
 
     # sampled cells
@@ -119,7 +124,7 @@ def test_c2_one_step_sampled_against_oracle():
         got = G[comp, cz, cy, cx]
         scale = max(np.abs(want).max(), np.abs(F0[comp]).max(), 1e-30)
         err = np.abs(got - want).max()
-        assert err <= TOL * scale, f"component {comp}: max error {err:.3e} against scale {scale:.3e}"
+        assert err <= tol * scale, f"component {comp}: max error {err:.3e} against scale {scale:.3e}"
 
 
 def test_c2_sampled_step_at_the_end_of_a_sort_interval():
