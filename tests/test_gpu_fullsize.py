@@ -53,19 +53,22 @@ def _neighbourhood_ids(wl, s, cells):
     return np.unique(np.concatenate(ids)) if ids else np.zeros(0, np.int64)
 
 
-@pytest.mark.parametrize("precision", [4, 8])
-def test_c2_one_step_sampled_against_oracle(precision):
+@pytest.mark.parametrize("precision,order", [(4, 2), (8, 2), (4, 3)])
+def test_c2_one_step_sampled_against_oracle(precision, order):
     # FP32 (the benchmark) at the workload's bar; FP64 (the same kernel
-    # compiled in double, two waves per SIMD) at the FP64 bar, 1e-12
+    # compiled in double, two waves per SIMD) at the FP64 bar, 1e-12; and
+    # the paper's cubic shapes in FP32 (a particle's deposit reaches two
+    # nodes below and three above its cell, inside REACH)
     import bench
     import oracle
     from paper_2104_11385_amd import picbal as pb
 
     wl = bench.workload()
     wl.precision = precision
+    wl.order = order
     tol = TOL if precision == 4 else 1e-12
     n = tuple(wl.n)
-    print(f"full-size parity: c2, precision {precision}, persistent + graph, 1 step", flush=True)
+    print(f"full-size parity: c2, precision {precision}, order {order}, persistent + graph, 1 step", flush=True)
     F0 = picsynth.random_fields(n, 7, amp=0.03)
     ctx = bench.ctx_for(wl)
     try:
