@@ -850,7 +850,9 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::EX <= A.n[0] && oy + C::EY <= A.n[1] &&
                                 oz + C::EZ <= A.n[2];
             const size_t sy = (size_t)A.n[0], sz = (size_t)A.n[0] * A.n[1];
-            for (int i = tid; i < C::NEB; i += nthr) {
+            for (int i0 = 0; i0 < C::NEB; i0 += nthr) {
+                const int i = i0 + tid;
+                if (i >= C::NEB) continue;
                 int lx = i % C::EX;
                 int r2 = i / C::EX;
                 int ly = r2 % C::EY;
@@ -868,12 +870,22 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                     }
                 }
                 const size_t g = (size_t)gx + sy * gy + sz * gz;
-                real v[6];
+                if constexpr (std::is_same<real, float>::value) {
+                    // straight from global memory into the window (each
+                    // lane's word lands at the wave's base + 4 * lane)
+                    const int wbase = i0 + (tid & ~63);
 #pragma unroll
-                for (int comp = 0; comp < 6; ++comp) v[comp] = A.EB[comp][g];
+                    for (int comp = 0; comp < 6; ++comp)
+                        __builtin_amdgcn_global_load_lds((const void *)&A.EB[comp][g], (void *)(sEB + comp * C::NEB + wbase), 4, 0, 0);
+                } else {
+                    real v[6];
 #pragma unroll
-                for (int comp = 0; comp < 6; ++comp) sEB[comp * C::NEB + i] = v[comp];
+                    for (int comp = 0; comp < 6; ++comp) v[comp] = A.EB[comp][g];
+#pragma unroll
+                    for (int comp = 0; comp < 6; ++comp) sEB[comp * C::NEB + i] = v[comp];
+                }
             }
+            if constexpr (std::is_same<real, float>::value) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         }
         if (tid == 0) {
             sCyc = 0;
