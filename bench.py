@@ -549,9 +549,9 @@ def mixed_box_generalisation(weights, X4, y4, steps=60, interval=10, ranks=96, e
     other models predict the same boxes: the one trained on the balancing
     study's 32^3-box runs alone (which never show these box sizes), and one
     trained on both layouts (the mixed-box samples repeated so that the two
-    layouts weigh the same).  Over three whole repetitions the mixed-box
-    model scored 0.994-0.996 of the clock's SFC efficiency at ~0.95%
-    cost-weighted error, the two-layout model 0.95-0.99 at ~1.5%."""
+    layouts weigh the same).  Over five whole repetitions the mixed-box
+    model scored 0.986-0.996 of the clock's SFC efficiency at ~1%
+    cost-weighted error, the two-layout model 0.93-0.99 at ~1.5%."""
     import picsynth
     from paper_2104_11385_amd import lb_study as S
     from paper_2104_11385_amd import picbal as pb
