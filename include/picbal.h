@@ -116,7 +116,7 @@ typedef struct {
  * every box edge and whose LDS windows let three 256-thread blocks share a
  * CU (else two, else one); block 256, chunk 4096, sort_interval 20,
  * blocks_per_cu = the number of blocks whose LDS fits on a CU (1..4),
- * run_sum 1. */
+ * run_sum 1, field_overlap 1. */
 typedef struct {
     int32_t tile[3];
     int32_t halo;          /* 1 */
@@ -131,6 +131,12 @@ typedef struct {
                               are interleaved over nodes (one particle per
                               node and rank) and each adds its own current.
                               Results agree to rounding either way.          */
+    int32_t field_overlap; /* 1: the Yee update of the z-planes that no
+                              deposit of the step can reach (no current in
+                              the previous step within two planes) runs on a
+                              second stream beside the particle kernel, the
+                              rest after it; 0: the whole update after it.
+                              The arithmetic is the same either way.         */
 } pic_tuning;
 
 /* ---- lifecycle -------------------------------------------------------- */

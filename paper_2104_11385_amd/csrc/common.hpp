@@ -87,10 +87,11 @@ struct GpdArgs {
     unsigned long long *rtc;       // [nb]
     const BoxMap *bmap;            // box bounds and the cell -> box map
     unsigned int *slow;            // particles that took the global path
+    int *slowlist;                 // [capacity] particles left to the global-path kernel
+    unsigned int *slown;           // [2] entries in slowlist, and blocks of the global kernel done
     int *jdirty;                   // [n[2]] set to 1 for every z-plane of J written
     int mode;
     int timer;                 // nonzero: per-box clock counters are updated
-    int staged;                // zero: no LDS windows, every particle on the global path
     int tile_base;             // PER_BOX: first tile of the box
     int species_only;          // PER_BOX: species of this launch
     const int4 *queue;         // PERSISTENT: (tile, begin, end, -)

@@ -1,6 +1,7 @@
 // Host side of the gather-push-deposit kernels: the compiled tile shapes,
 // their LDS footprint and the dispatch to the kernel groups (one object per
-// precision and shape order, built from gpd_inst.hip).
+// precision and shape order, built from gpd_inst.hip), and the global-path
+// kernel.
 #include "kernels.hpp"
 
 #include <hip/hip_runtime.h>
@@ -10,6 +11,8 @@ namespace pb {
 // Defined in gpd_kernel.hpp and instantiated once per (precision, order).
 template <typename real, int M>
 hipError_t gpd_tile(const GpdLaunch &L, hipStream_t st);
+template <typename real, int M>
+hipError_t gpd_global(const GpdLaunch &L, int n, unsigned grid, hipStream_t st);
 
 bool gpd_supported(const int tile[3], int halo) {
     if (halo != 1) return false;
@@ -34,6 +37,15 @@ hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st) {
     }
     if (order == 3) return gpd_tile<float, 3>(L, st);
     return order == 2 ? gpd_tile<float, 2>(L, st) : gpd_tile<float, 1>(L, st);
+}
+
+hipError_t launch_gpd_global(int prec, int order, const GpdLaunch &L, int n, unsigned grid, hipStream_t st) {
+    if (prec == 8) {
+        if (order == 3) return gpd_global<double, 3>(L, n, grid, st);
+        return order == 2 ? gpd_global<double, 2>(L, n, grid, st) : gpd_global<double, 1>(L, n, grid, st);
+    }
+    if (order == 3) return gpd_global<float, 3>(L, n, grid, st);
+    return order == 2 ? gpd_global<float, 2>(L, n, grid, st) : gpd_global<float, 1>(L, n, grid, st);
 }
 
 }  // namespace pb

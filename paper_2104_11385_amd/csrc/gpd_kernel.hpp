@@ -485,20 +485,10 @@ struct Deferred {
     real d0[3], D[3], coef;
 };
 
-template <typename real, int M, int TX, int TY, int TZ, int H, bool R>
-__device__ __forceinline__ void push_particle(const GpdArgs<real> &A, bool live, const PState<real> &ps,
-                                              const TileDesc &td, real hq, real cq, const real *sEB, double *sJ,
-                                              unsigned &nslow, Deferred<real> &df, PState<real> &out) {
-    using C = Cfg<real, M, TX, TY, TZ, H>;
-    int c[3];
-    unpack_cell(ps.cell, c[0], c[1], c[2]);
-    real f[3] = {ps.f[0], ps.f[1], ps.f[2]};
-    real u[3] = {ps.u[0], ps.u[1], ps.u[2]};
-    real w = ps.w;
-
-    // reference point: cell (order 1) or nearest node (order 2)
-    int ref[3];
-    real d0[3];
+// Reference point of a particle at cell c, offset f: the cell (orders 1
+// and 3) or the nearest node (order 2), and the offset d0 from it.
+template <typename real, int M>
+__device__ __forceinline__ void reference(const int c[3], const real f[3], int ref[3], real d0[3]) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (M == 2) {
@@ -510,40 +500,16 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, bool live,
             d0[d] = f[d];
         }
     }
-    const int T[3] = {TX, TY, TZ};
-    const int org[3] = {td.x0, td.y0, td.z0};
-    int rel[3];
-    bool fast = A.staged != 0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        rel[d] = wrap_rel(ref[d] - org[d], H, A.n[d]);
-        fast = fast && rel[d] <= T[d] + H - 1;
-    }
+}
 
-    GatherW<real, M> GW[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) GW[d].set(d0[d]);
-    real EB[6];
-    if (fast) {
-        LdsEB<real, C> acc{sEB, (rel[0] + H + C::RL_EB) + C::EX * ((rel[1] + H + C::RL_EB) + C::EY * (rel[2] + H + C::RL_EB)), 0};
-        gather6<real, M>(acc, GW, EB);
-    } else {
-        GlobEB<real> acc;
-        acc.EB = A.EB;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            acc.n[d] = A.n[d];
-            acc.r[d] = ref[d];
-        }
-        gather6<real, M>(acc, GW, EB);
-        nslow += live;  // stand-ins past the item's end do not count
-    }
+// Relativistic Boris rotation of u in the gathered fields EB (B without its
+// uniform external part, added here), and the displacement D over dt.
+template <typename real>
+__device__ __forceinline__ void boris_move(const GpdArgs<real> &A, real hq, real EB[6], real u[3], real D[3]) {
     // the arrays hold B minus its uniform external part (whose curl is zero)
     EB[3] += A.bext[0];
     EB[4] += A.bext[1];
     EB[5] += A.bext[2];
-
-    // relativistic Boris rotation
     real um[3] = {u[0] + hq * EB[0], u[1] + hq * EB[1], u[2] + hq * EB[2]};
     real ig = rsqrt_r((real)1 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
     real t[3] = {hq * EB[3] * ig, hq * EB[4] * ig, hq * EB[5] * ig};
@@ -556,12 +522,79 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, bool live,
     u[1] = um[1] + (up[2] * s[0] - up[0] * s[2]) + hq * EB[1];
     u[2] = um[2] + (up[0] * s[1] - up[1] * s[0]) + hq * EB[2];
     real gi = rsqrt_r((real)1 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    real D[3] = {A.dt * u[0] * gi, A.dt * u[1] * gi, A.dt * u[2] * gi};
+    D[0] = A.dt * u[0] * gi;
+    D[1] = A.dt * u[1] * gi;
+    D[2] = A.dt * u[2] * gi;
+}
+
+// New canonical position after the displacement D: cell + offset in [0, 1),
+// periodic wrap (a step below zero so small that x + 1 rounds to 1 keeps the
+// cell, at offset 0); selects rather than branches.
+template <typename real>
+__device__ __forceinline__ void advance(const GpdArgs<real> &A, int c[3], const real f[3], const real D[3],
+                                        const real u[3], PState<real> &out) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const real x = f[d] + D[d];
+        // |D| < 1: the floor is -1, 0 or 1, and x - floor(x) rounds as
+        // x + 1 or x - 1 would
+        const real fl = floor(x);
+        real y = x - fl;
+        int k = (int)fl;
+        const bool stay = y >= (real)1;
+        y = stay ? (real)0 : y;
+        k = stay ? 0 : k;
+        int cc = c[d] + k;
+        cc = cc < 0 ? cc + A.n[d] : (cc >= A.n[d] ? cc - A.n[d] : cc);
+        c[d] = cc;
+        out.f[d] = y;
+        out.u[d] = u[d];
+    }
+    out.cell = pack_cell(c[0], c[1], c[2]);
+}
+
+// Push of one particle whose gather and deposit stencils lie in the tile's
+// staged LDS windows; returns false when they do not.  Such a particle is
+// computed on a harmless in-window reference, its deposit record is left
+// empty (df as given), and the caller drops its results and leaves it to
+// the global-path kernel.
+template <typename real, int M, int TX, int TY, int TZ, int H, bool R>
+__device__ __forceinline__ bool push_staged(const GpdArgs<real> &A, const PState<real> &ps, const TileDesc &td,
+                                            real hq, real cq, const real *sEB, double *sJ, Deferred<real> &df,
+                                            PState<real> &out) {
+    using C = Cfg<real, M, TX, TY, TZ, H>;
+    int c[3];
+    unpack_cell(ps.cell, c[0], c[1], c[2]);
+    const real f[3] = {ps.f[0], ps.f[1], ps.f[2]};
+    real u[3] = {ps.u[0], ps.u[1], ps.u[2]};
+    int ref[3];
+    real d0[3];
+    reference<real, M>(c, f, ref, d0);
+    const int T[3] = {TX, TY, TZ};
+    const int org[3] = {td.x0, td.y0, td.z0};
+    int rel[3];
+    bool fast = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        rel[d] = wrap_rel(ref[d] - org[d], H, A.n[d]);
+        fast = fast && rel[d] <= T[d] + H - 1;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) rel[d] = fast ? rel[d] : 0;
+
+    GatherW<real, M> GW[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) GW[d].set(d0[d]);
+    real EB[6];
+    LdsEB<real, C> acc{sEB, (rel[0] + H + C::RL_EB) + C::EX * ((rel[1] + H + C::RL_EB) + C::EY * (rel[2] + H + C::RL_EB)), 0};
+    gather6<real, M>(acc, GW, EB);
+    real D[3];
+    boris_move(A, hq, EB, u, D);
 
     // Esirkepov deposit
-    real coef = cq * w;
-    bool moved = leaves_ref<real, M>(d0[0], D[0]) || leaves_ref<real, M>(d0[1], D[1]) ||
-                 leaves_ref<real, M>(d0[2], D[2]);
+    const real coef = cq * ps.w;
+    const bool moved = leaves_ref<real, M>(d0[0], D[0]) || leaves_ref<real, M>(d0[1], D[1]) ||
+                       leaves_ref<real, M>(d0[2], D[2]);
     // every lane's record is complete (finite values), whatever path it takes
     df.rel = (rel[0] + 8) | ((rel[1] + 8) << 8) | ((rel[2] + 8) << 16);
 #pragma unroll
@@ -578,10 +611,44 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, bool live,
             DepW<real, M> DW[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) DW[d].set_kept(d0[d], D[d]);
-            LdsJ<real, C> acc{sJ, (rel[0] + H + C::RL_J) + C::JX * ((rel[1] + H + C::RL_J) + C::JY * (rel[2] + H + C::RL_J)), 0};
-            deposit3<real, M, M + 1>(acc, DW, coef);
+            LdsJ<real, C> jacc{sJ, (rel[0] + H + C::RL_J) + C::JX * ((rel[1] + H + C::RL_J) + C::JY * (rel[2] + H + C::RL_J)), 0};
+            deposit3<real, M, M + 1>(jacc, DW, coef);
         }
-    } else if (live) {
+    }
+    advance(A, c, f, D, u, out);
+    return fast;
+}
+
+// Push of one particle through the global arrays (gather with periodic wrap,
+// deposit by global atomics): particles beyond their tile's staged windows,
+// and every particle when staging is off.
+template <typename real, int M>
+__device__ __forceinline__ void push_global(const GpdArgs<real> &A, const PState<real> &ps, real hq, real cq,
+                                            PState<real> &out) {
+    int c[3];
+    unpack_cell(ps.cell, c[0], c[1], c[2]);
+    const real f[3] = {ps.f[0], ps.f[1], ps.f[2]};
+    real u[3] = {ps.u[0], ps.u[1], ps.u[2]};
+    int ref[3];
+    real d0[3];
+    reference<real, M>(c, f, ref, d0);
+    GatherW<real, M> GW[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) GW[d].set(d0[d]);
+    real EB[6];
+    {
+        GlobEB<real> acc;
+        acc.EB = A.EB;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            acc.n[d] = A.n[d];
+            acc.r[d] = ref[d];
+        }
+        gather6<real, M>(acc, GW, EB);
+    }
+    real D[3];
+    boris_move(A, hq, EB, u, D);
+    {
         DepW<real, M> DW[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) DW[d].set(d0[d], D[d]);
@@ -593,34 +660,9 @@ __device__ __forceinline__ void push_particle(const GpdArgs<real> &A, bool live,
             acc.n[d] = A.n[d];
             acc.r[d] = ref[d];
         }
-        deposit3<real, M, M + 2>(acc, DW, coef);
+        deposit3<real, M, M + 2>(acc, DW, cq * ps.w);
     }
-
-    // new canonical position: cell + offset in [0, 1), periodic wrap (a
-    // step below zero so small that x + 1 rounds to 1 keeps the cell, at
-    // offset 0); selects rather than branches
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const real x = f[d] + D[d];
-        // |D| < 1: the floor is -1, 0 or 1, and x - floor(x) rounds as
-        // x + 1 or x - 1 would
-        const real fl = floor(x);
-        real y = x - fl;
-        int k = (int)fl;
-        const bool stay = y >= (real)1;
-        y = stay ? (real)0 : y;
-        k = stay ? 0 : k;
-        int cc = c[d] + k;
-        cc = cc < 0 ? cc + A.n[d] : (cc >= A.n[d] ? cc - A.n[d] : cc);
-        c[d] = cc;
-        f[d] = y;
-    }
-    out.cell = pack_cell(c[0], c[1], c[2]);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        out.f[d] = f[d];
-        out.u[d] = u[d];
-    }
+    advance(A, c, f, D, u, out);
 }
 
 // Deposits queue entry s (word k of slot s lives at q[k * stride + s]).
@@ -770,7 +812,6 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     real *qr = reinterpret_cast<real *>(smem_raw + C::lds);           // [7][blockDim.x]
     int *qi = reinterpret_cast<int *>(qr + 7 * blockDim.x);          // [blockDim.x]
     __shared__ unsigned long long sCyc, sRtc;
-    __shared__ unsigned int sSlow;
     __shared__ int sItem[3];
     __shared__ real sSpc[2 * kMaxSpecies];  // per species: q dt / (2 m), -q / dt
     __shared__ int sQn[8];  // queue lengths of the block's waves at the end of an item
@@ -845,7 +886,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
 
         // stage E and B of the tile window (one index computation serves the
         // six components; windows inside the domain need no wrap)
-        if (A.staged) {
+        {
             const int ox = td.x0 - H - C::RL_EB, oy = td.y0 - H - C::RL_EB, oz = td.z0 - H - C::RL_EB;
             const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::EX <= A.n[0] && oy + C::EY <= A.n[1] &&
                                 oz + C::EZ <= A.n[2];
@@ -890,7 +931,6 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
         if (tid == 0) {
             sCyc = 0;
             sRtc = 0;
-            sSlow = 0;
         }
         __syncthreads();
 
@@ -900,7 +940,6 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
             c0 = clock64();
             r0 = wall_clock64();
         }
-        unsigned nslow = 0;
         const int lane = tid & 63, qslot0 = tid & ~63;
         int qn = 0;  // entries in this wave's queue (wave-uniform)
         {
@@ -954,7 +993,10 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                     if (foreign) note_foreign(*A.bmap, cur.cell, sFBox, sFCnt, sFAny);
                 }
                 PState<real> moved;
-                push_particle<real, M, TX, TY, TZ, H, R>(A, p < se, cur, td, hq, cq, sEB, sJ, nslow, df, moved);
+                const bool fast = push_staged<real, M, TX, TY, TZ, H, R>(A, cur, td, hq, cq, sEB, sJ, df, moved);
+                // a particle beyond the windows is left to the global-path
+                // kernel, which runs after this one in the same step
+                if (!fast && p < se) A.slowlist[atomicAdd(A.slown, 1u)] = p;
                 if constexpr (R) deposit_runs<real, M, TX, TY, TZ, H>(df, sJ);
                 const unsigned long long mask = __ballot(df.want);
                 if (mask) {
@@ -978,7 +1020,7 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 // the next particle's loads are waited for before this one's
                 // stores are issued, so that the wait never covers the stores
                 nxt.settle();
-                if (p < se) moved.store(A.P, p);
+                if (p < se && fast) moved.store(A.P, p);
                 cur = nxt;
             }
         }
@@ -999,11 +1041,10 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                 atomicAdd(&sRtc, r1 - r0);
             }
         }
-        if (nslow) atomicAdd(&sSlow, nslow);
         __syncthreads();
 
         // flush the J window (nonzero entries only)
-        if (A.staged) {
+        {
             const int ox = td.x0 - H - C::RL_J, oy = td.y0 - H - C::RL_J, oz = td.z0 - H - C::RL_J;
             const bool inside = ox >= 0 && oy >= 0 && oz >= 0 && ox + C::JX <= A.n[0] && oy + C::JY <= A.n[1] &&
                                 oz + C::JZ <= A.n[2];
@@ -1075,9 +1116,69 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
                     atomicAdd(&A.rtc[td.box], rtc - rf);
                 }
             }
-            if (sSlow) atomicAdd(A.slow, sSlow);
         }
         __syncthreads();
+    }
+}
+
+// The global path as a kernel of its own, so that its registers do not add
+// to the tile kernel's: the particles listed in slowlist[0, slown[0]) (left
+// by the tile kernel, whose windows they have left), or particles [0, n)
+// with no list (staging off).  Each particle's work is charged to the box of
+// its cell at the start of the step, its wave's clock split evenly over the
+// wave's particles.  The last block to finish adds the count to the running
+// total of global-path particles and clears the list for the next step.
+template <typename real, int M>
+__global__ __launch_bounds__(256) void k_gpd_global(GpdArgs<real> A, int n) {
+    __shared__ unsigned sN;
+    if (threadIdx.x == 0) sN = A.slowlist ? A.slown[0] : (unsigned)n;
+    __syncthreads();
+    const int cnt = (int)sN;
+    const bool timed = A.timer != 0;
+    const int stride = gridDim.x * blockDim.x;
+    // the trip count is the same for every lane of a wave (clock reads are
+    // wave-wide)
+    for (int base = blockIdx.x * blockDim.x + (int)(threadIdx.x & ~63u); base < cnt; base += stride) {
+        const int k = base + (int)(threadIdx.x & 63u);
+        const bool live = k < cnt;
+        unsigned long long c0 = 0, r0 = 0;
+        if (timed) {
+            c0 = clock64();
+            r0 = wall_clock64();
+        }
+        int box = 0;
+        if (live) {
+            const int p = A.slowlist ? A.slowlist[k] : k;
+            PState<real> cur;
+            cur.load(A.P, p);
+            const int sp = A.P.sp[p];
+            int x, y, z;
+            unpack_cell(cur.cell, x, y, z);
+            const BoxMap &bm = *A.bmap;
+            box = bm.coarse_box[(x / bm.g[0]) + bm.cg[0] * ((y / bm.g[1]) + bm.cg[1] * (z / bm.g[2]))];
+            PState<real> moved;
+            push_global<real, M>(A, cur, A.h[sp], A.coefq[sp], moved);
+            moved.store(A.P, p);
+        }
+        if (timed && live) {
+            const unsigned long long c1 = clock64(), r1 = wall_clock64();
+            const unsigned long long nl = (unsigned long long)__popcll(__ballot(1));
+            atomicAdd(&A.cycles[box], (c1 - c0) / nl);
+            atomicAdd(&A.rtc[box], (r1 - r0) / nl);
+        }
+    }
+    if (!A.slowlist) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && cnt > 0) atomicAdd(A.slow, (unsigned)cnt);
+        return;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(A.slown + 1, 1u) == gridDim.x - 1) {
+            if (cnt > 0) atomicAdd(A.slow, (unsigned)cnt);
+            A.slown[0] = 0;
+            A.slown[1] = 0;
+        }
     }
 }
 
@@ -1099,19 +1200,9 @@ static Particles<real> cast(const ParticlesRaw &r) {
     return p;
 }
 
-// Table of compiled gather-push-deposit variants.
-template <typename real, int M, int TX, int TY, int TZ, int H, bool R>
-static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
-    using C = Cfg<real, M, TX, TY, TZ, H>;
-    auto kern = k_gpd<real, M, TX, TY, TZ, H, R>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(C::lds + 512 * C::qslot));
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    if (L.block != 256 && L.block != 384 && L.block != 512) return hipErrorInvalidValue;
+// Kernel arguments from the precision-erased launch description.
+template <typename real>
+static GpdArgs<real> gpd_args_of(const GpdLaunch &L) {
     GpdArgs<real> A;
     A.P = cast<real>(L.P);
     A.segstart = L.segstart;
@@ -1130,15 +1221,33 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
     A.rtc = L.rtc;
     A.bmap = L.bmap;
     A.slow = L.slow;
+    A.slowlist = L.slowlist;
+    A.slown = L.slown;
     A.jdirty = L.jdirty;
     A.mode = L.mode;
     A.timer = L.timer;
-    A.staged = L.staged;
     A.tile_base = L.tile_base;
     A.species_only = L.species_only;
     A.queue = L.queue;
     A.queue_bounds = L.queue_bounds;
     A.queue_head = L.queue_head;
+    return A;
+}
+
+// Table of compiled gather-push-deposit variants.
+template <typename real, int M, int TX, int TY, int TZ, int H, bool R>
+static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
+    using C = Cfg<real, M, TX, TY, TZ, H>;
+    auto kern = k_gpd<real, M, TX, TY, TZ, H, R>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(C::lds + 512 * C::qslot));
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (L.block != 256 && L.block != 384 && L.block != 512) return hipErrorInvalidValue;
+    GpdArgs<real> A = gpd_args_of<real>(L);
     if (L.grid == 0) return hipSuccess;
     kern<<<L.grid, L.block, C::lds + (size_t)L.block * C::qslot, st>>>(A);
     return hipGetLastError();
@@ -1158,6 +1267,17 @@ static hipError_t gpd_tile_r(const GpdLaunch &L, hipStream_t st) {
 template <typename real, int M>
 hipError_t gpd_tile(const GpdLaunch &L, hipStream_t st) {
     return L.run_sum ? gpd_tile_r<real, M, true>(L, st) : gpd_tile_r<real, M, false>(L, st);
+}
+
+// The global-path kernel: over the tile kernels' list (n < 0), or over
+// particles [0, n) with no list.
+template <typename real, int M>
+hipError_t gpd_global(const GpdLaunch &L, int n, unsigned grid, hipStream_t st) {
+    GpdArgs<real> A = gpd_args_of<real>(L);
+    if (n >= 0) A.slowlist = nullptr;
+    if (grid == 0) return hipSuccess;
+    k_gpd_global<real, M><<<grid, 256, 0, st>>>(A, n < 0 ? 0 : n);
+    return hipGetLastError();
 }
 
 }  // namespace pb

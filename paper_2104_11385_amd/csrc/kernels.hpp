@@ -77,10 +77,12 @@ struct GpdLaunch {
     unsigned long long *cycles, *rtc;
     const BoxMap *bmap;        // device copy of the box bounds and map
     unsigned int *slow;
+    int *slowlist;             // [capacity] list of the particles left to the global-path kernel
+    unsigned int *slown;       // [2] its length and a completion counter (zero between steps)
     int *jdirty;               // [nz] z-planes of J the deposit touched
     int mode;
     int timer;
-    int staged;
+    int staged;                // zero: every particle through the global-path kernel
     int tile_base;
     int species_only;
     const int4 *queue;
@@ -103,6 +105,9 @@ hipError_t launch_fill_u64(unsigned long long *a, size_t n, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st, uint32_t v = 0);
 hipError_t launch_fill_f64(double *a, size_t n, hipStream_t st);
 hipError_t launch_gpd(int prec, int order, const GpdLaunch &L, hipStream_t st);
+// The global path: over the tile kernels' list (n < 0), or every particle
+// [0, n) (staging off); grid blocks of 256 threads.
+hipError_t launch_gpd_global(int prec, int order, const GpdLaunch &L, int n, unsigned grid, hipStream_t st);
 bool gpd_supported(const int tile[3], int halo);
 size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo, int block);
 // Field buffers of one Yee update: inputs E, B, J; outputs Eo, Bo; Z is the
@@ -111,16 +116,24 @@ size_t gpd_lds_bytes(int prec, int order, const int tile[3], int halo, int block
 // launch_yee (launch_yee_half computes it from E and B) and B^{n+3/2} on
 // exit; outputs Eo, Bo; Z is the J buffer cleared for the next deposit.
 // jdirty / zdirty: per z-plane occupancy flags of J and Z (0: the plane is
-// zero); launch_yee resets zdirty.
+// zero); the second part of launch_yee resets zdirty.  lists: [4 nz + 4]
+// plane lists and counts written by launch_yee_class.
 struct YeeBuffers {
     const void *E[3], *B[3], *J[3];
     void *X[3];
     void *Eo[3], *Bo[3], *Z[3];
     const int *jdirty;
     int *zdirty;
+    int *lists;
 };
 hipError_t launch_yee_half(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
-hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
+// Splits the z-planes into those no deposit of the coming step reaches (all
+// planes go to the second part when split is false).
+hipError_t launch_yee_class(const YeeBuffers &Y, int nz, bool split, hipStream_t st);
+// E and B passes of one part: 0 the planes out of the deposit's reach (may
+// run beside the particle kernel), 1 the rest (after it); grid blocks.
+hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, int part, unsigned grid,
+                      hipStream_t st);
 hipError_t launch_find_ids(int prec, const ParticlesRaw &P, int np, int s, const int64_t *q, int n, uint32_t *cell,
                            void *f, void *u, int *found, hipStream_t st);
 hipError_t launch_box_counts(int prec, const ParticlesRaw &P, int np, const Geom &G, unsigned long long *counts,

@@ -371,10 +371,8 @@ __global__ void k_fill(T *a, T v, size_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Yee update in streaming passes.  Each thread owns an (x, y) column over
-// YSZ z-planes (one plane with the current blocks), carrying the z
-// neighbour in registers along the march; x and y neighbours are read
-// through the caches.  X is a half-step B buffer.
+// Yee update in streaming passes.  Each thread updates one cell; its
+// neighbours are read through the caches.  X is a half-step B buffer.
 //   half:  X = B^{n+1/2} = B^n - dt/2 curl E^n (only when X is not current)
 //   E:     E^{n+1} = E^n + dt (curl X - J) into the other E buffer, and the
 //          next step's J buffer cleared; z-planes that the deposit left
@@ -383,12 +381,22 @@ __global__ void k_fill(T *a, T v, size_t n) {
 //          X = B^{n+1} - dt/2 curl E^{n+1} = B^{n+3/2}, the next step's half
 //          step (the same curl, so the next update skips the half pass)
 // Curl of E uses forward differences, curl of B backward ones (Yee cell).
+//
+// The E and B passes run over lists of z-planes.  The planes are split in
+// two parts before each step: those that no deposit of the step can reach
+// (no current in the previous step within two planes; particles move less
+// than a cell per step, and a particle's stencil at the start of a step was
+// covered by the previous step's deposit), updated on a second stream while
+// the particle kernel runs, and the rest, updated after it.
 // ---------------------------------------------------------------------------
 
-// A Yee block is 256 threads over a row segment of 2^lx cells in x and
+// A Yee work unit is 256 threads over a row segment of 2^lx cells in x and
 // 256 / 2^lx rows in y, in one z-plane; the widest segment that divides n_x
 // (256, 128 or 64 cells) is used.  Measured on 256^3 cells against 64 x 4
 // blocks marching 4 planes: the two passes take 0.264 ms instead of 0.293.
+// The half pass launches one block per unit (YSZ planes each); the E and B
+// passes run a fixed grid of blocks that step through their plane list's
+// units.
 constexpr int YSZ = 1;
 
 struct YeeArgs {
@@ -397,9 +405,89 @@ struct YeeArgs {
     void *Eo[3], *Bo[3], *Z[3];
     const int *jdirty;      // [nz] 0: plane of J known to be zero
     int *zdirty;            // [nz] the same for Z; reset by the B pass once Z is clear
+    const int *planes;      // z-planes of this pass
+    const int *nplanes;     // their number (device memory)
+    int quiet;              // nonzero: planes no deposit of the step reaches (J, Z not read)
     int n[3];
     int lx;                 // log2 of the block's extent in x
     double dt;
+};
+
+// Plane lists of the split update (four lists of nz entries, then four
+// counts): 0 and 1 the E and B planes out of the deposit's reach, 2 and 3
+// the others.  E of plane k is out of reach when Z (the previous step's
+// current) is clear on planes k-2..k+2.  B of plane k reads E^{n+1} of
+// planes k and k+1, and its new half-step B is read by the E update of plane
+// k+1: it joins the early part only when E of both planes does.  split = 0
+// puts every plane in lists 2 and 3.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_yee_class(const int *zdirty, int nz, int split, int *lists) {
+    __shared__ int wsum[16][4];
+    __shared__ int base[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int *cnt = lists + 4 * (size_t)nz;
+    if (tid < 4) base[tid] = 0;
+    __syncthreads();
+    for (int k0 = 0; k0 < nz; k0 += 1024) {
+        const int k = k0 + tid;
+        bool qe = false, qb = false;
+        if (k < nz && split) {
+            bool quiet[2] = {true, true};
+            for (int d = -2; d <= 3; ++d) {
+                const int q = ((k + d) % nz + nz) % nz;
+                const bool z = zdirty[q] == 0;
+                if (d <= 2) quiet[0] = quiet[0] && z;
+                if (d >= -1) quiet[1] = quiet[1] && z;
+            }
+            qe = quiet[0];
+            qb = quiet[0] && quiet[1];
+        }
+        const bool in[4] = {k < nz && qe, k < nz && qb, k < nz && !qe, k < nz && !qb};
+        unsigned long long m[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) m[l] = __ballot(in[l]);
+        if (lane == 0)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) wsum[w][l] = __popcll(m[l]);
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            if (!in[l]) continue;
+            int off = base[l] + __popcll(m[l] & ((1ull << lane) - 1ull));
+            for (int v = 0; v < w; ++v) off += wsum[v][l];
+            lists[(size_t)l * nz + off] = k;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            int t = 0;
+            for (int v = 0; v < 16; ++v) t += wsum[v][tid];
+            base[tid] += t;
+        }
+        __syncthreads();
+    }
+    if (tid < 4) cnt[tid] = base[tid];
+}
+
+// Work units of a pass over a plane list: unit u is row segment u mod P of
+// plane list[u / P] (P segments per plane).  The block steps through units
+// u = blockIdx.x + i gridDim.x; the next unit's plane is loaded before the
+// current unit is computed.
+struct YeeUnits {
+    int P, gx, nunit, stride;
+    int u, k;  // current unit and its plane
+    __device__ __forceinline__ YeeUnits(const YeeArgs &a) {
+        gx = (a.n[0] + (1 << a.lx) - 1) >> a.lx;
+        P = gx * ((a.n[1] + (256 >> a.lx) - 1) / (256 >> a.lx));
+        nunit = P * *a.nplanes;
+        stride = gridDim.x;
+        u = blockIdx.x;
+        k = u < nunit ? a.planes[u / P] : 0;
+    }
+    // the cell of this thread in unit u
+    __device__ __forceinline__ void cell(const YeeArgs &a, int &x, int &y) const {
+        const int r = u % P, by = r / gx, bx = r - by * gx;
+        x = (bx << a.lx) + (int)(threadIdx.x & ((1u << a.lx) - 1u));
+        y = by * (256 >> a.lx) + (int)(threadIdx.x >> a.lx);
+    }
 };
 
 template <typename real>
@@ -440,22 +528,24 @@ __global__ __launch_bounds__(256) void k_yee_bhalf(YeeArgs a) {
 template <typename real>
 __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
     const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-    const int x = ((int)blockIdx.x << a.lx) + (int)(threadIdx.x & ((1u << a.lx) - 1u));
-    const int y = (int)blockIdx.y * (256 >> a.lx) + (int)(threadIdx.x >> a.lx);
-    if (x >= nx || y >= ny) return;
-    const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
     const real dt = (real)a.dt;
     const real *Ex = (const real *)a.E[0], *Ey = (const real *)a.E[1], *Ez = (const real *)a.E[2];
     const real *Jx = (const real *)a.J[0], *Jy = (const real *)a.J[1], *Jz = (const real *)a.J[2];
     const real *Hx = (const real *)a.X[0], *Hy = (const real *)a.X[1], *Hz = (const real *)a.X[2];
     const size_t sxy = (size_t)nx * ny;
-    const int xm = x == 0 ? nx - 1 : x - 1, ym = y == 0 ? ny - 1 : y - 1;
-    const size_t c0 = (size_t)x + (size_t)nx * y, cxm = (size_t)xm + (size_t)nx * y, cym = (size_t)x + (size_t)nx * ym;
-    const size_t gm = sxy * (z0 == 0 ? nz - 1 : z0 - 1);
-    real hx_m = Hx[c0 + gm], hy_m = Hy[c0 + gm];
-    for (int k = z0; k < z1; ++k) {
-        const size_t gk = sxy * k, g = c0 + gk;
-        const bool jd = a.jdirty[k] != 0, zd = a.zdirty[k] != 0;
+    for (YeeUnits w(a); w.u < w.nunit;) {
+        const int k = w.k;
+        int x, y;
+        w.cell(a, x, y);
+        const int un = w.u + w.stride;
+        w.k = un < w.nunit ? a.planes[un / w.P] : 0;
+        w.u = un;
+        if (x >= nx || y >= ny) continue;
+        const int xm = x == 0 ? nx - 1 : x - 1, ym = y == 0 ? ny - 1 : y - 1;
+        const size_t c0 = (size_t)x + (size_t)nx * y, cxm = (size_t)xm + (size_t)nx * y, cym = (size_t)x + (size_t)nx * ym;
+        const size_t gk = sxy * k, g = c0 + gk, gm = sxy * (k == 0 ? nz - 1 : k - 1);
+        const bool jd = !a.quiet && a.jdirty[k] != 0, zd = !a.quiet && a.zdirty[k] != 0;
+        const real hx_m = Hx[c0 + gm], hy_m = Hy[c0 + gm];
         const real hx = Hx[g], hy = Hy[g], hz = Hz[g];
         const real hzym = Hz[cym + gk], hzxm = Hz[cxm + gk], hyxm = Hy[cxm + gk], hxym = Hx[cym + gk];
         real jx = (real)0, jy = (real)0, jz = (real)0;
@@ -472,36 +562,36 @@ __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
             ((real *)a.Z[1])[g] = (real)0;
             ((real *)a.Z[2])[g] = (real)0;
         }
-        hx_m = hx;
-        hy_m = hy;
     }
 }
 
 template <typename real>
 __global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
     const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-    const int z0 = blockIdx.z * YSZ, z1 = min(nz, z0 + YSZ);
-    // the E pass (earlier on the stream) has cleared Z: its planes are zero
-    if (blockIdx.x == 0 && blockIdx.y == 0 && (int)threadIdx.x < z1 - z0) a.zdirty[z0 + threadIdx.x] = 0;
-    const int x = ((int)blockIdx.x << a.lx) + (int)(threadIdx.x & ((1u << a.lx) - 1u));
-    const int y = (int)blockIdx.y * (256 >> a.lx) + (int)(threadIdx.x >> a.lx);
-    if (x >= nx || y >= ny) return;
     const real hdt = (real)(0.5 * a.dt);
     const real *Ex = (const real *)a.Eo[0], *Ey = (const real *)a.Eo[1], *Ez = (const real *)a.Eo[2];
     real *Hx = (real *)a.X[0], *Hy = (real *)a.X[1], *Hz = (real *)a.X[2];
     const size_t sxy = (size_t)nx * ny;
-    const int xp = x + 1 == nx ? 0 : x + 1, yp = y + 1 == ny ? 0 : y + 1;
-    const size_t col = (size_t)x + (size_t)nx * y, colx = (size_t)xp + (size_t)nx * y,
-                 coly = (size_t)x + (size_t)nx * yp;
-    size_t g = col + sxy * z0;
-    real ex = Ex[g], ey = Ey[g];
-    for (int k = z0; k < z1; ++k) {
-        const size_t gk = sxy * k, gn = sxy * (k + 1 == nz ? 0 : k + 1);
+    for (YeeUnits w(a); w.u < w.nunit;) {
+        const int k = w.k;
+        int x, y;
+        w.cell(a, x, y);
+        // the E pass (earlier on the stream) has cleared Z: its planes are
+        // zero (the early part's planes were clear already)
+        if (!a.quiet && threadIdx.x == 0 && w.u % w.P == 0) a.zdirty[k] = 0;
+        const int un = w.u + w.stride;
+        w.k = un < w.nunit ? a.planes[un / w.P] : 0;
+        w.u = un;
+        if (x >= nx || y >= ny) continue;
+        const int xp = x + 1 == nx ? 0 : x + 1, yp = y + 1 == ny ? 0 : y + 1;
+        const size_t col = (size_t)x + (size_t)nx * y, colx = (size_t)xp + (size_t)nx * y,
+                     coly = (size_t)x + (size_t)nx * yp;
+        const size_t gk = sxy * k, gn = sxy * (k + 1 == nz ? 0 : k + 1), g = col + gk;
+        const real ex = Ex[g], ey = Ey[g];
         const real exn = Ex[col + gn], eyn = Ey[col + gn];
-        const real ez = Ez[col + gk];
+        const real ez = Ez[g];
         const real eyx = Ey[colx + gk], ezx = Ez[colx + gk];
         const real exy = Ex[coly + gk], ezy = Ez[coly + gk];
-        g = col + gk;
         const real cx = (ezy - ez) - (eyn - ey);
         const real cy = (exn - ex) - (ezx - ez);
         const real cz = (eyx - ey) - (exy - ex);
@@ -512,8 +602,6 @@ __global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
         Hx[g] = bx - hdt * cx;
         Hy[g] = by - hdt * cy;
         Hz[g] = bz - hdt * cz;
-        ex = exn;
-        ey = eyn;
     }
 }
 
@@ -827,6 +915,9 @@ static YeeArgs yee_args(const YeeBuffers &Y, const int n[3], double dt) {
     }
     a.jdirty = Y.jdirty;
     a.zdirty = Y.zdirty;
+    a.planes = nullptr;
+    a.nplanes = nullptr;
+    a.quiet = 0;
     a.lx = yee_lx(n);
     a.dt = dt;
     return a;
@@ -844,14 +935,29 @@ hipError_t launch_yee_half(int prec, const YeeBuffers &Y, const int n[3], double
     return hipGetLastError();
 }
 
-hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st) {
+hipError_t launch_yee_class(const YeeBuffers &Y, int nz, bool split, hipStream_t st) {
+    k_yee_class<<<1, 1024, 0, st>>>(Y.zdirty, nz, split ? 1 : 0, Y.lists);
+    return hipGetLastError();
+}
+
+hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, int part, unsigned grid,
+                      hipStream_t st) {
+    if (grid == 0) return hipSuccess;
     YeeArgs a = yee_args(Y, n, dt);
+    a.quiet = part == 0 ? 1 : 0;
+    const int le = part == 0 ? 0 : 2;  // the part's E list; its B list follows
+    const size_t nz = (size_t)n[2];
+    YeeArgs b = a;
+    a.planes = Y.lists + le * nz;
+    a.nplanes = Y.lists + 4 * nz + le;
+    b.planes = Y.lists + (le + 1) * nz;
+    b.nplanes = Y.lists + 4 * nz + le + 1;
     if (prec == 8) {
-        k_yee_e<double><<<yee_grid(n), 256, 0, st>>>(a);
-        k_yee_b2<double><<<yee_grid(n), 256, 0, st>>>(a);
+        k_yee_e<double><<<grid, 256, 0, st>>>(a);
+        k_yee_b2<double><<<grid, 256, 0, st>>>(b);
     } else {
-        k_yee_e<float><<<yee_grid(n), 256, 0, st>>>(a);
-        k_yee_b2<float><<<yee_grid(n), 256, 0, st>>>(a);
+        k_yee_e<float><<<grid, 256, 0, st>>>(a);
+        k_yee_b2<float><<<grid, 256, 0, st>>>(b);
     }
     return hipGetLastError();
 }

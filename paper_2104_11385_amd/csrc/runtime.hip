@@ -225,6 +225,9 @@ GpdLaunch pic_ctx::gpd_args() const {
     L.rtc = d_rtc;
     L.bmap = d_bmap;
     L.slow = d_slow;
+    // the sort's rank array is idle between sorts
+    L.slowlist = (int *)W.rank;
+    L.slown = d_slown;
     L.jdirty = d_jdirty[jcur];
     L.mode = mode;
     L.timer = cost_timer ? 1 : 0;
@@ -263,8 +266,31 @@ int pic_ctx::time_end() {
 int pic_ctx::enqueue_step() {
     GpdLaunch L = gpd_args();
     int rc;
+    // the field update of the planes that no deposit of this step reaches
+    // runs on the second stream beside the particle kernels (it needs what
+    // the previous step left: E^n, the half-step B and the current flags)
+    YeeBuffers Y = yee_buffers();
+    const bool split = tun.field_overlap != 0;
+    // the early part takes two blocks per CU, so that it fits beside the
+    // particle kernel's blocks whichever is dispatched first; with fewer
+    // particles than half the cells the particle kernel is the shorter branch
+    // (about 50 ps per particle against 27 ps per cell for two blocks per CU)
+    // and the early part takes eight
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    const unsigned yee_early = (unsigned)((2 * np >= cells ? 2 : 8) * n_cu), yee_grid = (unsigned)(64 * n_cu);
+    HIPC(launch_yee_class(Y, n[2], split, st));
+    if (split) {
+        HIPC(hipEventRecord(ev_fork, st));
+        HIPC(hipStreamWaitEvent(st2, ev_fork, 0));
+        HIPC(launch_yee(prec, Y, n, dt, 0, yee_early, st2));
+        HIPC(hipEventRecord(ev_join, st2));
+    }
     if ((rc = time_begin(0))) return rc;
-    if (mode == MODE_PER_BOX) {
+    if (!staged) {
+        // reference path: every particle through the global arrays
+        const unsigned g = (unsigned)std::min<int64_t>((np + 255) / 256, (int64_t)n_cu * 8);
+        HIPC(launch_gpd_global(prec, order, L, (int)np, g, st));
+    } else if (mode == MODE_PER_BOX) {
         for (int b = 0; b < nb; ++b)
             for (int s = 0; s < nsp; ++s) {
                 L.tile_base = h_box_tile_off[b];
@@ -280,10 +306,13 @@ int pic_ctx::enqueue_step() {
         L.grid = (unsigned)(n_cu * std::max(1, tun.blocks_per_cu));
         HIPC(launch_gpd(prec, order, L, st));
     }
+    // the particles the tile kernels left to the global path (rare: those
+    // that drifted beyond their tile's windows since the last sort)
+    if (staged) HIPC(launch_gpd_global(prec, order, L, -1, (unsigned)n_cu, st));
     if ((rc = time_end())) return rc;
+    if (split) HIPC(hipStreamWaitEvent(st, ev_join, 0));
     if ((rc = time_begin(1))) return rc;
-    YeeBuffers Y = yee_buffers();
-    HIPC(launch_yee(prec, Y, n, dt, st));
+    HIPC(launch_yee(prec, Y, n, dt, 1, yee_grid, st));
     if ((rc = time_end())) return rc;
     return PIC_OK;
 }
@@ -309,6 +338,7 @@ YeeBuffers pic_ctx::yee_buffers() const {
     }
     Y.jdirty = d_jdirty[jcur];
     Y.zdirty = d_jdirty[1 - jcur];
+    Y.lists = d_ylists;
     return Y;
 }
 
@@ -434,6 +464,8 @@ int pic_ctx::upload(const std::vector<uint32_t> &cell, const std::vector<double>
     }
     if ((rc = put(R.w, w))) return rc;
     drop_graphs();
+    // new positions: every plane of J may be reached by the next deposit
+    if (mark_j_dirty()) return fail(PIC_EDEVICE, "J plane flags");
     return sort_now();
 }
 
@@ -446,8 +478,12 @@ pic_ctx::~pic_ctx() {
             (void)hipEventDestroy(e.second);
         }
     mlp_release();
+    if (st2) (void)hipStreamSynchronize(st2);
     for (void *p : allocs) (void)hipFree(p);
     if (own_stream) (void)hipStreamDestroy(st);
+    if (st2) (void)hipStreamDestroy(st2);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
 }
 
 // ---------------------------------------------------------------------------
@@ -586,6 +622,10 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
             return init_fail(c, PIC_EDEVICE, "hipStreamCreate failed");
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+        return init_fail(c, PIC_EDEVICE, "stream or event creation failed");
 
     // default tuning: the largest compiled tile that divides every box edge
     // and leaves room for three resident 256-thread blocks per CU, else for
@@ -595,6 +635,7 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     c->tun.chunk = 4096;
     c->tun.sort_interval = 20;
     c->tun.run_sum = 1;
+    c->tun.field_overlap = 1;
     const int cand[4][3] = {{8, 4, 4}, {4, 4, 4}, {8, 8, 4}, {8, 8, 8}};
     bool chosen = false;
     for (size_t limit : {(size_t)kLdsPerCu / 3, (size_t)kLdsPerCu / 2, (size_t)kLdsPerCu}) {
@@ -647,8 +688,10 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
     if ((rc = c->dalloc((void **)&c->d_cycles, 8 * (size_t)n_boxes)) ||
         (rc = c->dalloc((void **)&c->d_rtc, 8 * (size_t)n_boxes)) ||
         (rc = c->dalloc((void **)&c->d_slow, sizeof(unsigned))) ||
+        (rc = c->dalloc((void **)&c->d_slown, 2 * sizeof(unsigned))) ||
         (rc = c->dalloc((void **)&c->d_jdirty[0], sizeof(int) * (size_t)c->n[2])) ||
         (rc = c->dalloc((void **)&c->d_jdirty[1], sizeof(int) * (size_t)c->n[2])) ||
+        (rc = c->dalloc((void **)&c->d_ylists, sizeof(int) * (4 * (size_t)c->n[2] + 4))) ||
         (rc = c->dalloc((void **)&c->d_counts, 8 * (size_t)n_boxes * n_species)))
         return init_fail(c, rc, "");
     // box geometry
@@ -692,7 +735,8 @@ PIC_API int pic_init(const pic_grid_desc *grid, const pic_box *boxes, int32_t n_
             return init_fail(c, PIC_EDEVICE, "field initialisation failed");
     }
     if (launch_fill_u64(c->d_cycles, n_boxes, c->st) || launch_fill_u64(c->d_rtc, n_boxes, c->st) ||
-        launch_fill_u32((uint32_t *)c->d_slow, 1, c->st) || c->mark_j_dirty() ||
+        launch_fill_u32((uint32_t *)c->d_slow, 1, c->st) || launch_fill_u32((uint32_t *)c->d_slown, 2, c->st) ||
+        c->mark_j_dirty() ||
         launch_fill_u32((uint32_t *)c->Q.cls_cnt, (size_t)kSubQueues * c->Q.ncls, c->st))
         return init_fail(c, PIC_EDEVICE, "counter initialisation failed");
 
@@ -790,6 +834,8 @@ PIC_API int pic_set_tuning(pic_ctx *ctx, const pic_tuning *t) {
     if (t->chunk < 64 || t->sort_interval < 1 || t->blocks_per_cu < 1 || t->blocks_per_cu > 16)
         return ctx->fail(PIC_EINVAL, "chunk >= 64, sort_interval >= 1, 1 <= blocks_per_cu <= 16");
     if (t->run_sum != 0 && t->run_sum != 1) return ctx->fail(PIC_EINVAL, "run_sum must be 0 or 1");
+    if (t->field_overlap != 0 && t->field_overlap != 1)
+        return ctx->fail(PIC_EINVAL, "field_overlap must be 0 or 1");
     if (!gpd_supported(t->tile, t->halo)) return ctx->fail(PIC_EUNSUPPORTED, "tile shape not compiled");
     if (gpd_lds_bytes(ctx->prec, ctx->order, t->tile, t->halo, t->block) > kLdsPerCu)
         return ctx->fail(PIC_EUNSUPPORTED, "tile needs more LDS than a CU has");

@@ -44,6 +44,10 @@ struct pic_ctx {
     int dev = 0, n_cu = 256;
     hipStream_t st = nullptr;
     bool own_stream = false;
+    // second stream for the field update of the z-planes out of the step's
+    // deposit reach, forked from and joined back into st by events
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     pic_tuning tun{};
     int mode = PIC_LAUNCH_PERSISTENT;
     bool use_graph = false;
@@ -86,7 +90,9 @@ struct pic_ctx {
     // costs
     unsigned long long *d_cycles = nullptr, *d_rtc = nullptr, *d_counts = nullptr;
     unsigned *d_slow = nullptr;
+    unsigned *d_slown = nullptr;  // [2] global-path list length and completion counter
     int *d_jdirty[2] = {nullptr, nullptr};  // per z-plane: J buffer b may be nonzero there
+    int *d_ylists = nullptr;                 // [4 nz + 4] plane lists of the split field update
     std::vector<double> last_timer;      // last device-timer costs read
     std::vector<double> last_pred;       // learned prediction made for the current interval
     double mare = -1.0;                  // last mean relative error of the learned costs

@@ -43,12 +43,12 @@ class pic_species_desc(ctypes.Structure):
 
 class pic_tuning(ctypes.Structure):
     _fields_ = [("tile", i32 * 3), ("halo", i32), ("block", i32), ("chunk", i32),
-                ("sort_interval", i32), ("blocks_per_cu", i32), ("run_sum", i32)]
+                ("sort_interval", i32), ("blocks_per_cu", i32), ("run_sum", i32), ("field_overlap", i32)]
 
     def as_dict(self):
         return {"tile": list(self.tile), "halo": self.halo, "block": self.block, "chunk": self.chunk,
                 "sort_interval": self.sort_interval, "blocks_per_cu": self.blocks_per_cu,
-                "run_sum": self.run_sum}
+                "run_sum": self.run_sum, "field_overlap": self.field_overlap}
 
 
 class PicError(RuntimeError):

@@ -106,6 +106,29 @@ def test_graph_replay_across_sorts(precision, mode):
     compare(ctx, wl, x, u, w, sp, ids, F, 14, TOL[precision])
 
 
+@pytest.mark.parametrize("precision,order,graph", [(8, 2, False), (8, 3, True), (4, 2, True)])
+def test_field_update_split_follows_a_drifting_slab(precision, order, graph):
+    # a thin electron slab drifting at 0.89c along z into planes that held no
+    # current: each step the Yee update of the planes out of the deposit's
+    # reach runs beside the particle kernel and the rest after it, and the
+    # slab keeps entering planes of the first kind (within its tiles' windows
+    # between sorts, beyond them on the global path); with and without the
+    # split the step matches the oracle
+    wl = picsynth.small_workload(n=(16, 16, 64), box=8, order=order, ppc=2, seed=31, species=("electrons",),
+                                 u_th=0.05, precision=precision, region_lo=(0, 0, 8), region_hi=(16, 16, 12),
+                                 u_drift=(0.0, 0.0, 2.0))
+    nsteps = 30 if precision == 8 else 10
+    for ov in (1, 0):
+        print(f"[parity] drifting slab precision={precision} order={order} graph={graph} overlap={ov}", flush=True)
+        ctx = make_ctx(wl, load=False)
+        ctx.set_tuning(field_overlap=ov, sort_interval=7)
+        ctx.set_launch_mode(2, graph)
+        F0 = picsynth.random_fields(wl.n, 23, amp=0.02)
+        x, u, w, ids, sp, F = set_state(ctx, wl, F0)
+        ctx.step(nsteps)
+        compare(ctx, wl, x, u, w, sp, ids, F, nsteps, TOL[precision])
+
+
 @pytest.mark.parametrize("precision,order", [(8, 2), (4, 2), (8, 3), (4, 1)])
 def test_fast_particles_take_global_path(precision, order):
     # u_th = 0.6: particles drift several cells between sorts, beyond the
