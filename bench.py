@@ -223,6 +223,17 @@ def run_gpu(args):
     timer_stats["gpd_ms_timer_off"] = float(np.median(off_ms))
     timer_stats["overhead"] = float(np.median(on_ms) / np.median(off_ms) - 1.0)
     timer_stats["steps_per_leg"] = nsteps
+    # the same step with the whole field update after the particle kernel
+    # (no planes updated on the second stream beside it): step time from
+    # graph replays, and the particle kernel's time on its own
+    overlap_off = None
+    if not args.quick:
+        ctx.set_tuning(field_overlap=0)
+        g_off = float(np.median([timed(mode, True, args.steps, 2, False)[0] for _ in range(3)]))
+        _, k_off, n_off = timed(mode, False, args.steps, 2, True)
+        ctx.set_tuning(field_overlap=tun.field_overlap)
+        overlap_off = {"ms_per_step_graph": g_off, "gpd_ms": k_off[0] / max(1, n_off[0]),
+                       "yee_ms": k_off[1] / max(1, n_off[1])}
     # the unstaged reference: every particle gathers from and deposits into
     # global memory directly (no LDS windows), same launch mode
     unstaged = None
@@ -240,7 +251,7 @@ def run_gpu(args):
         "gpd_ms": gpd_ms, "gpd_launches_per_step": float(kn[0]) / (REPS * args.steps),
         "yee_ms": kms[1] / max(1, kn[1]), "sort_ms_total": kms[2] / REPS, "gpd_bytes": gpd_bytes,
         "step_bytes": step_bytes, "modes_ms": extra, "tuning": tun.as_dict(), "slow_path": slow,
-        "timer_costs": timer_stats, "unstaged": unstaged,
+        "timer_costs": timer_stats, "unstaged": unstaged, "overlap_off": overlap_off,
     }
 
 
@@ -699,7 +710,12 @@ def main():
                      "frac": gpd_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "gather-push-deposit", "kernel_ms": r["gpd_ms"],
                      "algorithmic_bytes_per_launch": r["gpd_bytes"],
-                     "measured_copy_peak": copy_gbs, "frac_of_copy_peak": gpd_gbs / copy_gbs},
+                     "measured_copy_peak": copy_gbs, "frac_of_copy_peak": gpd_gbs / copy_gbs,
+                     # kernel_ms is taken while the early field update shares
+                     # the CUs; the kernel on its own (field update after it):
+                     "kernel_ms_alone": r["overlap_off"]["gpd_ms"] if r["overlap_off"] else None,
+                     "frac_alone": (r["gpd_bytes"] / (r["overlap_off"]["gpd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                    if r["overlap_off"] else None)},
         "step_hbm_frac": r["step_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "modes_ms_per_step": r["modes_ms"],
         "modes_step_hbm_frac": {k: (r["step_bytes"] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS if v else None)
@@ -709,7 +725,10 @@ def main():
                  "eager_ms_per_step": r["eager_reps"],
                  "value_from": "median of the graph-replay repetitions (one graph launch per step, sorts "
                                "included); kernel times from HIP events in the eager repetitions"},
+        # with the field update split, the Yee passes timed here are those
+        # that follow the particle kernel; the others run beside it
         "yee_ms": r["yee_ms"], "slow_path_particles": r["slow_path"],
+        "field_overlap_off": r["overlap_off"],
         "timer_costs": r["timer_costs"],
         "unstaged_reference_kernel": r["unstaged"],
         # the same kernel against the vector-ALU peak
