@@ -554,9 +554,12 @@ __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
             jy = Jy[g];
             jz = Jz[g];
         }
-        ((real *)a.Eo[0])[g] = Ex[g] + dt * (((hz - hzym) - (hy - hy_m)) - jx);
-        ((real *)a.Eo[1])[g] = Ey[g] + dt * (((hx - hx_m) - (hz - hzxm)) - jy);
-        ((real *)a.Eo[2])[g] = Ez[g] + dt * (((hy - hyxm) - (hx - hxym)) - jz);
+        // every load before the first store (the output buffers could alias
+        // the inputs as far as the compiler knows)
+        const real ex = Ex[g], ey = Ey[g], ez = Ez[g];
+        ((real *)a.Eo[0])[g] = ex + dt * (((hz - hzym) - (hy - hy_m)) - jx);
+        ((real *)a.Eo[1])[g] = ey + dt * (((hx - hx_m) - (hz - hzxm)) - jy);
+        ((real *)a.Eo[2])[g] = ez + dt * (((hy - hyxm) - (hx - hxym)) - jz);
         if (zd) {
             ((real *)a.Z[0])[g] = (real)0;
             ((real *)a.Z[1])[g] = (real)0;
@@ -576,9 +579,6 @@ __global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
         const int k = w.k;
         int x, y;
         w.cell(a, x, y);
-        // the E pass (earlier on the stream) has cleared Z: its planes are
-        // zero (the early part's planes were clear already)
-        if (!a.quiet && threadIdx.x == 0 && w.u % w.P == 0) a.zdirty[k] = 0;
         const int un = w.u + w.stride;
         w.k = un < w.nunit ? a.planes[un / w.P] : 0;
         w.u = un;
@@ -603,6 +603,13 @@ __global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
         Hy[g] = by - hdt * cy;
         Hz[g] = bz - hdt * cz;
     }
+    // the E pass (earlier on the stream) has cleared Z: its planes are zero
+    // (the early part's planes were clear already); done after the loop, so
+    // that the loop's plane-list loads stay scalar loads
+    if (!a.quiet)
+        for (int zi = (int)(blockIdx.x * blockDim.x + threadIdx.x); zi < *a.nplanes;
+             zi += (int)(gridDim.x * blockDim.x))
+            a.zdirty[a.planes[zi]] = 0;
 }
 
 // ---------------------------------------------------------------------------

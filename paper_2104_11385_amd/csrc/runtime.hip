@@ -277,7 +277,14 @@ int pic_ctx::enqueue_step() {
     // (about 50 ps per particle against 27 ps per cell for two blocks per CU)
     // and the early part takes eight
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    const unsigned yee_early = (unsigned)((2 * np >= cells ? 2 : 8) * n_cu), yee_grid = (unsigned)(64 * n_cu);
+    const unsigned yee_early = (unsigned)((2 * np >= cells ? 2 : 8) * n_cu);
+    // the rest: 64 blocks per CU, or enough that no block takes more than
+    // eight units (row segments) of the plane list; blocks that step through
+    // more units lose the neighbour planes they share from the caches
+    // (512^3, all planes after the particle kernel: 3.06 ms per update with
+    // 32 units per block, 2.70 with 8; 256^3: 0.26 ms with 4)
+    const size_t units = ((size_t)n[0] * n[1] + 255) / 256 * (size_t)n[2];
+    const unsigned yee_grid = (unsigned)std::max<size_t>((size_t)64 * n_cu, (units + 7) / 8);
     HIPC(launch_yee_class(Y, n[2], split, st));
     if (split) {
         HIPC(hipEventRecord(ev_fork, st));
