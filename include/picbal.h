@@ -353,16 +353,19 @@ PIC_API int pic_mlp_get_weights(pic_ctx *ctx, float *w, int64_t n);
 PIC_API int pic_set_cost_timer(pic_ctx *ctx, int32_t enable);
 
 /* LDS staging of the tile windows on (enable != 0, the default) or off.
- * Off, the gather-push-deposit kernel stages nothing: every particle
- * gathers E and B from the global field arrays and adds its current to the
- * global J with atomics (the path that particles beyond the staged halo
- * take).  Results agree to rounding; this is the unstaged reference the
+ * Off, no tile kernel runs and nothing is staged: the global-path kernel
+ * pushes every particle, gathering E and B from the global field arrays and
+ * adding its current to the global J with atomics (the path that particles
+ * beyond the staged halo take).  Results agree to rounding; this is the unstaged reference the
  * staged kernel is measured against.  Synchronises the stream when the
  * setting changes; pic_slow_path_count then counts every particle. */
 PIC_API int pic_set_staging(pic_ctx *ctx, int32_t enable);
 
 /* With enable != 0 the library brackets each launch of the gather-push-
- * deposit kernel and of the field update with HIP events on its stream. */
+ * deposit kernels (tile and global-path kernel together) and of the field
+ * update with HIP events on its stream.  With field_overlap set, the field
+ * update so timed is the part that follows the particle kernel; the part
+ * beside it runs on the library's second stream and is not timed. */
 PIC_API int pic_kernel_timing(pic_ctx *ctx, int32_t enable);
 
 /* ms[4] = total milliseconds of {gather-push-deposit, field update, sort,

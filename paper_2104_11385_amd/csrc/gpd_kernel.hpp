@@ -19,7 +19,10 @@
 // order), the currents of lanes whose particles keep a common reference node
 // are summed across the lanes of each 16-lane row (and across one row
 // boundary) before one LDS add per run; particles that change node wait in a
-// per-wave queue for a wider deposit on full waves.
+// per-wave queue for a wider deposit on full waves.  A particle whose
+// stencils leave the windows (it drifted beyond the halo since the last
+// sort) is listed, and a second kernel pushes the listed particles through
+// the global arrays after the tile kernel.
 #pragma once
 
 #include "device_util.hpp"
