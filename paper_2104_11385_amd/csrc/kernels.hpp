@@ -99,7 +99,6 @@ hipError_t launch_sort(int prec, const ParticlesRaw &S, const ParticlesRaw &D, i
                        const SortScratch &W, bool node_major, hipStream_t st);
 hipError_t launch_queue(const int *segstart, int ntiles, int nsp, int chunk, const QueueScratch &Q, hipStream_t st);
 hipError_t launch_set_int(int *p, int v, hipStream_t st);
-hipError_t launch_reset_heads(int *heads, hipStream_t st);
 hipError_t launch_fill_f(int prec, void *a, double v, size_t n, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *a, size_t n, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *a, size_t n, hipStream_t st, uint32_t v = 0);
@@ -128,8 +127,9 @@ struct YeeBuffers {
 };
 hipError_t launch_yee_half(int prec, const YeeBuffers &Y, const int n[3], double dt, hipStream_t st);
 // Splits the z-planes into those no deposit of the coming step reaches (all
-// planes go to the second part when split is false).
-hipError_t launch_yee_class(const YeeBuffers &Y, int nz, bool split, hipStream_t st);
+// planes go to the second part when split is false); with heads non-null it
+// also zeroes the persistent queue's kSubQueues sub-queue heads.
+hipError_t launch_yee_class(const YeeBuffers &Y, int nz, bool split, int *heads, hipStream_t st);
 // E and B passes of one part: 0 the planes out of the deposit's reach (may
 // run beside the particle kernel), 1 the rest (after it); grid blocks.
 hipError_t launch_yee(int prec, const YeeBuffers &Y, const int n[3], double dt, int part, unsigned grid,

@@ -355,10 +355,6 @@ __global__ void k_queue_fill(const int *segstart, int ntiles, int nsp, int chunk
     if (rem) queue[pr] = make_int4(t, b + full * chunk, b + n, 0);
 }
 
-__global__ void k_reset_heads(int *heads) {
-    if (threadIdx.x < kSubQueues && blockIdx.x == 0) heads[threadIdx.x] = 0;
-}
-
 __global__ void k_set_int(int *p, int v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
@@ -419,12 +415,15 @@ struct YeeArgs {
 // current) is clear on planes k-2..k+2.  B of plane k reads E^{n+1} of
 // planes k and k+1, and its new half-step B is read by the E update of plane
 // k+1: it joins the early part only when E of both planes does.  split = 0
-// puts every plane in lists 2 and 3.  One block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_yee_class(const int *zdirty, int nz, int split, int *lists) {
+// puts every plane in lists 2 and 3.  One block of 1024 threads; it also
+// rewinds the persistent work queue's sub-queue heads (heads non-null), as
+// it runs ahead of the particle kernel.
+__global__ __launch_bounds__(1024) void k_yee_class(const int *zdirty, int nz, int split, int *lists, int *heads) {
     __shared__ int wsum[16][4];
     __shared__ int base[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     int *cnt = lists + 4 * (size_t)nz;
+    if (heads && tid < kSubQueues) heads[tid] = 0;
     if (tid < 4) base[tid] = 0;
     __syncthreads();
     for (int k0 = 0; k0 < nz; k0 += 1024) {
@@ -555,15 +554,17 @@ __global__ __launch_bounds__(256) void k_yee_e(YeeArgs a) {
             jz = Jz[g];
         }
         // every load before the first store (the output buffers could alias
-        // the inputs as far as the compiler knows)
+        // the inputs as far as the compiler knows); the stores carry the
+        // non-temporal hint, which leaves the caches to the planes still
+        // being read (and to the particle kernel beside the early part)
         const real ex = Ex[g], ey = Ey[g], ez = Ez[g];
-        ((real *)a.Eo[0])[g] = ex + dt * (((hz - hzym) - (hy - hy_m)) - jx);
-        ((real *)a.Eo[1])[g] = ey + dt * (((hx - hx_m) - (hz - hzxm)) - jy);
-        ((real *)a.Eo[2])[g] = ez + dt * (((hy - hyxm) - (hx - hxym)) - jz);
+        __builtin_nontemporal_store(ex + dt * (((hz - hzym) - (hy - hy_m)) - jx), &((real *)a.Eo[0])[g]);
+        __builtin_nontemporal_store(ey + dt * (((hx - hx_m) - (hz - hzxm)) - jy), &((real *)a.Eo[1])[g]);
+        __builtin_nontemporal_store(ez + dt * (((hy - hyxm) - (hx - hxym)) - jz), &((real *)a.Eo[2])[g]);
         if (zd) {
-            ((real *)a.Z[0])[g] = (real)0;
-            ((real *)a.Z[1])[g] = (real)0;
-            ((real *)a.Z[2])[g] = (real)0;
+            __builtin_nontemporal_store((real)0, &((real *)a.Z[0])[g]);
+            __builtin_nontemporal_store((real)0, &((real *)a.Z[1])[g]);
+            __builtin_nontemporal_store((real)0, &((real *)a.Z[2])[g]);
         }
     }
 }
@@ -596,12 +597,13 @@ __global__ __launch_bounds__(256) void k_yee_b2(YeeArgs a) {
         const real cy = (exn - ex) - (ezx - ez);
         const real cz = (eyx - ey) - (exy - ex);
         const real bx = Hx[g] - hdt * cx, by = Hy[g] - hdt * cy, bz = Hz[g] - hdt * cz;
-        ((real *)a.Bo[0])[g] = bx;
-        ((real *)a.Bo[1])[g] = by;
-        ((real *)a.Bo[2])[g] = bz;
-        Hx[g] = bx - hdt * cx;
-        Hy[g] = by - hdt * cy;
-        Hz[g] = bz - hdt * cz;
+        // non-temporal stores, as in the E pass
+        __builtin_nontemporal_store(bx, &((real *)a.Bo[0])[g]);
+        __builtin_nontemporal_store(by, &((real *)a.Bo[1])[g]);
+        __builtin_nontemporal_store(bz, &((real *)a.Bo[2])[g]);
+        __builtin_nontemporal_store(bx - hdt * cx, &Hx[g]);
+        __builtin_nontemporal_store(by - hdt * cy, &Hy[g]);
+        __builtin_nontemporal_store(bz - hdt * cz, &Hz[g]);
     }
     // the E pass (earlier on the stream) has cleared Z: its planes are zero
     // (the early part's planes were clear already); done after the loop, so
@@ -871,10 +873,6 @@ hipError_t launch_set_int(int *p, int v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_reset_heads(int *heads, hipStream_t st) {
-    k_reset_heads<<<1, 64, 0, st>>>(heads);
-    return hipGetLastError();
-}
 
 hipError_t launch_fill_f(int prec, void *a, double v, size_t n, hipStream_t st) {
     unsigned g = (unsigned)std::min<size_t>(8192, (n + 255) / 256);
@@ -942,8 +940,8 @@ hipError_t launch_yee_half(int prec, const YeeBuffers &Y, const int n[3], double
     return hipGetLastError();
 }
 
-hipError_t launch_yee_class(const YeeBuffers &Y, int nz, bool split, hipStream_t st) {
-    k_yee_class<<<1, 1024, 0, st>>>(Y.zdirty, nz, split ? 1 : 0, Y.lists);
+hipError_t launch_yee_class(const YeeBuffers &Y, int nz, bool split, int *heads, hipStream_t st) {
+    k_yee_class<<<1, 1024, 0, st>>>(Y.zdirty, nz, split ? 1 : 0, Y.lists, heads);
     return hipGetLastError();
 }
 

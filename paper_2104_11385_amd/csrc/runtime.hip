@@ -285,7 +285,8 @@ int pic_ctx::enqueue_step() {
     // 32 units per block, 2.70 with 8; 256^3: 0.26 ms with 4)
     const size_t units = ((size_t)n[0] * n[1] + 255) / 256 * (size_t)n[2];
     const unsigned yee_grid = (unsigned)std::max<size_t>((size_t)64 * n_cu, (units + 7) / 8);
-    HIPC(launch_yee_class(Y, n[2], split, st));
+    // (the same one-block kernel rewinds the persistent queue's heads)
+    HIPC(launch_yee_class(Y, n[2], split, mode == MODE_PERSISTENT && staged ? Q.queue_head : nullptr, st));
     if (split) {
         HIPC(hipEventRecord(ev_fork, st));
         HIPC(hipStreamWaitEvent(st2, ev_fork, 0));
@@ -309,7 +310,6 @@ int pic_ctx::enqueue_step() {
         L.grid = (unsigned)ntiles;
         HIPC(launch_gpd(prec, order, L, st));
     } else {
-        HIPC(launch_reset_heads(Q.queue_head, st));
         L.grid = (unsigned)(n_cu * std::max(1, tun.blocks_per_cu));
         HIPC(launch_gpd(prec, order, L, st));
     }
