@@ -823,6 +823,9 @@ __global__ __launch_bounds__(512) void k_gpd(GpdArgs<real> A) {
     __shared__ int sFBox[kForeignSlots];
     __shared__ unsigned sFCnt[kForeignSlots];
     __shared__ unsigned sFAny;
+    // the field update's early part may share the CUs, and has slack: this
+    // kernel's waves take instruction-issue priority over its waves
+    __builtin_amdgcn_s_setprio(1);
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nsp = A.nsp;
     const int home = blockIdx.x % kSubQueues;  // blocks are dealt round-robin over the XCDs
