@@ -185,3 +185,41 @@ def test_comm_volume_mixed_boxes_small():
     rank = rng.integers(0, 5, len(boxes)).astype(np.int32)
     per, _ = pb.lb_comm_volume(boxes, (32, 32, 32), rank, 5, 2.0)
     np.testing.assert_array_equal(per, oracle.comm_volume((32, 32, 32), boxes, rank, 5, 2.0))
+
+
+def _header_structs():
+    """Field lists (type, name, count) of the header's typedef'd structs."""
+    import re
+    text = open(os.path.join(ROOT, "include", "picbal.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct \{(.*?)\}\s*(\w+);", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = " ".join(decl.split())
+            if not decl:
+                continue
+            m = re.match(r"((?:const )?[\w]+(?: \*)?)\s*(.*)", decl)
+            ctype = m.group(1).replace(" *", "*")
+            for item in m.group(2).split(","):
+                item = item.strip()
+                if item.startswith("*"):
+                    ctype, item = ctype + "*", item[1:].strip()
+                mm = re.match(r"(\w+)(?:\[(\d+)\])?", item)
+                fields.append((ctype, mm.group(1), int(mm.group(2) or 1)))
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_match_the_header():
+    # the ctypes structures of the binding list the header's fields in the
+    # same order with the same widths, so the two agree on every offset
+    import ctypes
+    from paper_2104_11385_amd import picbal as pb
+    width = {"int32_t": 4, "int64_t": 8, "uint64_t": 8, "double": 8, "float": 4}
+    hs = _header_structs()
+    for name in ("pic_box", "pic_grid_desc", "pic_species_desc", "pic_tuning"):
+        cls = getattr(pb, name)
+        got = [(f[0], ctypes.sizeof(f[1])) for f in cls._fields_]
+        want = [(n, (8 if t.endswith("*") else width[t]) * k) for t, n, k in hs[name]]
+        assert got == want, name
