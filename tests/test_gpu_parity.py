@@ -106,8 +106,9 @@ def test_graph_replay_across_sorts(precision, mode):
     compare(ctx, wl, x, u, w, sp, ids, F, 14, TOL[precision])
 
 
-@pytest.mark.parametrize("precision,order,graph", [(8, 2, False), (8, 3, True), (4, 2, True)])
-def test_field_update_split_follows_a_drifting_slab(precision, order, graph):
+@pytest.mark.parametrize("precision,order,mode,graph", [(8, 2, 2, False), (8, 3, 2, True), (4, 2, 2, True),
+                                                       (4, 2, 0, False), (8, 1, 1, True)])
+def test_field_update_split_follows_a_drifting_slab(precision, order, mode, graph):
     # a thin electron slab drifting at 0.89c along z into planes that held no
     # current: each step the Yee update of the planes out of the deposit's
     # reach runs beside the particle kernel and the rest after it, and the
@@ -119,10 +120,11 @@ def test_field_update_split_follows_a_drifting_slab(precision, order, graph):
                                  u_drift=(0.0, 0.0, 2.0))
     nsteps = 30 if precision == 8 else 10
     for ov in (1, 0):
-        print(f"[parity] drifting slab precision={precision} order={order} graph={graph} overlap={ov}", flush=True)
+        print(f"[parity] drifting slab precision={precision} order={order} mode={mode} graph={graph} overlap={ov}",
+              flush=True)
         ctx = make_ctx(wl, load=False)
         ctx.set_tuning(field_overlap=ov, sort_interval=7)
-        ctx.set_launch_mode(2, graph)
+        ctx.set_launch_mode(mode, graph)
         F0 = picsynth.random_fields(wl.n, 23, amp=0.02)
         x, u, w, ids, sp, F = set_state(ctx, wl, F0)
         ctx.step(nsteps)
