@@ -548,7 +548,7 @@ def lb_study(steps=300, interval=10, ranks=96, train_seeds=(4, 6), eval_seed=5, 
     return out
 
 
-def mixed_box_generalisation(weights, X4, y4, steps=60, interval=10, ranks=96, epochs=1000,
+def mixed_box_generalisation(weights, X4, y4, steps=120, interval=10, ranks=96, epochs=1000,
                              tables=((19, 11), (23, 13), (29, 17), (31, 19)), eval_steps=120):
     """The learned cost on the 4096 mixed boxes (64^3, 32^3, 16^3) of the
     512^3 workload.  Training: four mixed-box runs whose box ppc tables come
@@ -561,10 +561,11 @@ def mixed_box_generalisation(weights, X4, y4, steps=60, interval=10, ranks=96, e
     other models predict the same boxes: the one trained on the balancing
     study's 32^3-box runs alone (which never show these box sizes), and one
     trained on both layouts (the mixed-box samples repeated so that the two
-    layouts weigh the same).  With a 60-step held-out run (5 rebalances),
-    nine whole repetitions put the mixed-box model at 0.978-1.002 of the
-    clock's SFC efficiency at ~1% cost-weighted error, the two-layout model
-    at 0.93-0.99 at ~1.5%."""
+    layouts weigh the same).  With 60-step training and held-out runs (5
+    rebalances), nine whole repetitions put the mixed-box model at
+    0.978-1.002 of the clock's SFC efficiency at ~1% cost-weighted error,
+    the two-layout model at 0.93-0.99 at ~1.5%; a model trained on 60-step
+    runs predicts steps 60-120 at up to 2.3%."""
     import picsynth
     from paper_2104_11385_amd import lb_study as S
     from paper_2104_11385_amd import picbal as pb
@@ -623,7 +624,7 @@ def mixed_box_generalisation(weights, X4, y4, steps=60, interval=10, ranks=96, e
             "interval": interval, "ranks": ranks,
             "wall_s": time.perf_counter() - t_start,
             "workload": "512^3, 4096 mixed boxes, lognormal box ppc (held out: table seed 3, loader seed 12; "
-                        "training runs: tables 19, 23, 29, 31, loader seeds 11, 13, 17, 19, 60 steps each; "
+                        "training runs: tables 19, 23, 29, 31, loader seeds 11, 13, 17, 19, 120 steps each; "
                         "particles re-sorted every 10 steps), quadratic, FP32"}
 
 
