@@ -1141,12 +1141,33 @@ __global__ __launch_bounds__(256) void k_gpd_global(GpdArgs<real> A, int n) {
     __syncthreads();
     const int cnt = (int)sN;
     const bool timed = A.timer != 0;
-    const int stride = gridDim.x * blockDim.x;
+    const int stride = gridDim.x * blockDim.x, lane = (int)(threadIdx.x & 63u);
     // the trip count is the same for every lane of a wave (clock reads are
-    // wave-wide)
-    for (int base = blockIdx.x * blockDim.x + (int)(threadIdx.x & ~63u); base < cnt; base += stride) {
-        const int k = base + (int)(threadIdx.x & 63u);
-        const bool live = k < cnt;
+    // wave-wide); the next particle's loads are issued before this one is
+    // computed
+    int base = blockIdx.x * blockDim.x + (int)(threadIdx.x & ~63u);
+    PState<real> cur;
+    int p = 0, sp = 0;
+    bool live = base + lane < cnt;
+    if (live) {
+        p = A.slowlist ? A.slowlist[base + lane] : base + lane;
+        cur.load(A.P, p);
+        sp = A.P.sp[p];
+    } else {
+        cur.blank(0);
+    }
+    for (; base < cnt; base += stride) {
+        const int kn = base + stride + lane;
+        const bool live_n = kn < cnt;
+        PState<real> nxt;
+        int pn = 0, spn = 0;
+        if (live_n) {
+            pn = A.slowlist ? A.slowlist[kn] : kn;
+            nxt.load(A.P, pn);
+            spn = A.P.sp[pn];
+        } else {
+            nxt.blank(0);
+        }
         unsigned long long c0 = 0, r0 = 0;
         if (timed) {
             c0 = clock64();
@@ -1154,10 +1175,6 @@ __global__ __launch_bounds__(256) void k_gpd_global(GpdArgs<real> A, int n) {
         }
         int box = 0;
         if (live) {
-            const int p = A.slowlist ? A.slowlist[k] : k;
-            PState<real> cur;
-            cur.load(A.P, p);
-            const int sp = A.P.sp[p];
             int x, y, z;
             unpack_cell(cur.cell, x, y, z);
             const BoxMap &bm = *A.bmap;
@@ -1166,7 +1183,12 @@ __global__ __launch_bounds__(256) void k_gpd_global(GpdArgs<real> A, int n) {
             push_global<real, M>(A, cur, A.h[sp], A.coefq[sp], moved);
             moved.store(A.P, p);
         }
-        if (timed && live) {
+        const bool was_live = live;
+        cur = nxt;
+        p = pn;
+        sp = spn;
+        live = live_n;
+        if (timed && was_live) {
             const unsigned long long c1 = clock64(), r1 = wall_clock64();
             const unsigned long long nl = (unsigned long long)__popcll(__ballot(1));
             atomicAdd(&A.cycles[box], (c1 - c0) / nl);
