@@ -162,7 +162,9 @@ PIC_API void pic_finalize(pic_ctx *ctx);
  * J^{n+1/2}, periodic wrap, then the Yee update (B half step, E full step
  * with -J, B half step).  Particles are re-sorted by tile every
  * sort_interval steps.  Device-timer costs accumulate per box.  Asynchronous
- * on the context's stream.  n_steps < 0 -> PIC_EINVAL. */
+ * on the context's stream (with field_overlap, part of the field update runs
+ * on a second stream of the library's, joined back into the context's stream
+ * within the step).  n_steps < 0 -> PIC_EINVAL. */
 PIC_API int pic_step(pic_ctx *ctx, int32_t n_steps);
 
 /* Waits for all work queued on the context's stream. */
