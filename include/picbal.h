@@ -112,10 +112,13 @@ typedef struct {
  * 8x8x4, 8x4x4, 4x4x4) and divide every box edge; halo is the number of
  * cells a particle may drift outside its tile between sorts and still use the
  * staged fields (particles beyond it take a slower global-memory path).
- * pic_init's default: the first of 8x4x4, 4x4x4, 8x8x4, 8x8x8 that divides
- * every box edge and whose LDS windows let three 256-thread blocks share a
- * CU (else two, else one); block 256, chunk 4096, sort_interval 20,
- * blocks_per_cu = the number of blocks whose LDS fits on a CU (1..4),
+ * pic_init's default: 8x4x4 tiles, block 512, blocks_per_cu 2 where that
+ * tile divides every box edge, two such blocks' LDS fit a CU and the
+ * kernel's registers leave room for four waves per SIMD (the FP32 kernels of
+ * shape orders 1 and 2); else the first of 8x4x4, 4x4x4, 8x8x4, 8x8x8 that
+ * divides every box edge and whose LDS windows let three 256-thread blocks
+ * share a CU (else two, else one), block 256, blocks_per_cu = the number of
+ * blocks whose LDS fits on a CU (1..4); chunk 4096, sort_interval 20,
  * run_sum 1, field_overlap 1. */
 typedef struct {
     int32_t tile[3];

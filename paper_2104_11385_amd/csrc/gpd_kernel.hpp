@@ -1275,6 +1275,12 @@ static hipError_t gpd_one(const GpdLaunch &L, hipStream_t st) {
         attr = true;
     }
     if (L.block != 256 && L.block != 384 && L.block != 512) return hipErrorInvalidValue;
+    if (L.regs_out) {
+        hipFuncAttributes fa;
+        hipError_t e = hipFuncGetAttributes(&fa, (const void *)kern);
+        if (e != hipSuccess) return e;
+        *L.regs_out = fa.numRegs;
+    }
     GpdArgs<real> A = gpd_args_of<real>(L);
     if (L.grid == 0) return hipSuccess;
     kern<<<L.grid, L.block, C::lds + (size_t)L.block * C::qslot, st>>>(A);

@@ -92,6 +92,7 @@ struct GpdLaunch {
     int halo;
     int run_sum;               // kept-node currents summed over lane runs
     unsigned grid, block;
+    int *regs_out;             // non-null: receives the kernel's VGPRs per lane (grid 0: query only)
 };
 
 hipError_t launch_load(int prec, const ParticlesRaw &P, const LoadArgs &a, hipStream_t st);
